@@ -1,0 +1,257 @@
+"""Plain FP64 CPU oracle for gradient-decomposed multislice ptychography.
+
+TEST INFRASTRUCTURE ONLY.  This module is the slow, obviously-correct
+reference that the GPU path is checked against.  Only the test suite, the
+package smoke check and the benchmark's CPU-baseline leg may import it; the
+product path never does.  It shares no code, table or helper with the HIP
+library: it is written directly from the paper's statement of the problem
+with numpy's FFT as the only library primitive.
+
+What it computes (per probe location i with window top-left corner (y0, x0)):
+
+* Multislice model G (Section II-B, the paragraph after Eq. 1): the incident
+  wave is the probe; at each slice the wave is multiplied by the slice's
+  transmission over the window, then propagated to the next slice by a Fourier
+  transform, a multiplication by the Fresnel propagator and an inverse Fourier
+  transform; the output of one slice feeds the next.  The detector sees the
+  Fourier transform of the last exit wave.
+* Amplitude cost (Eq. 1): f_i = sum_q (|y_i| - |G(p_i, V)|)^2 with |y_i| the
+  square root of the measured intensity (reading of |y_i| as the measured
+  amplitude) and the modulus taken per detector pixel.
+* Gradient (Eq. 2): dF/dV = sum_i df_i/dV, each term non-zero only inside
+  window i (Section III).  The complex gradient is dF/dRe t + i dF/dIm t with
+  respect to the complex slice transmissions t_s.
+* Decomposition (Section III; the tile/halo construction): positions are
+  assigned to tiles, each tile accumulates the gradients of its own positions
+  on its halo-extended box, and the global gradient is the sum of the embedded
+  tile gradients (the one-device form of the neighbour add and the final
+  stitch of Alg. 1).
+* Full-batch gradient descent t <- t - alpha * G (Section II-B, last paragraph
+  of the formulation; the tile update of Alg. 1).
+
+Conventions: F is the unnormalised forward DFT (numpy ``fft2``); F^-1 carries
+1/M^2 (numpy ``ifft2``); frequencies are ``fftfreq(M, d=pixel)``; the
+propagator is H = exp(-i pi lambda dz |k|^2); intensities are in unshifted DFT
+order (DC at [0, 0]).
+
+Pins (tests/test_oracle_pins.py): brute-force DFT sums on tiny grids,
+Parseval, the flat-object closed form, a localised absorber (window
+orientation), propagator vs the exact angular-spectrum phase, slice-order
+special cases, translation and global-phase covariance, zero gradient at the
+truth, central finite differences, the adjoint dot-product identity, torch
+autograd on tiny grids, the decomposition sum, tile binning by brute force,
+and monotone descent.  ``gd_step_size`` is a reading (the paper states no step
+size): its descent property is tested, its value is not pinned ("parity
+unpinned" for the step length itself).
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Sequence, Tuple
+
+import numpy as np
+
+__all__ = [
+    "fresnel_propagator",
+    "exit_waves",
+    "forward",
+    "loss_and_gradient",
+    "position_loss_and_patch_gradients",
+    "tile_bounds",
+    "bin_positions",
+    "extended_box",
+    "tile_gradient",
+    "stitch_tile_gradients",
+    "gd_step_size",
+    "gd_step",
+]
+
+
+# ---------------------------------------------------------------------------
+# Physics: the Fresnel propagator between slices (Section II-B; the propagator
+# form exp(-i pi lambda dz |k|^2) is the paraxial free-space transfer function).
+# ---------------------------------------------------------------------------
+def fresnel_propagator(M: int, wavelength: float, dz: float, pixel: float) -> np.ndarray:
+    """H[ky, kx] = exp(-i pi lambda dz (ky^2 + kx^2)), k = fftfreq(M, d=pixel); complex128 [M, M]."""
+    k = np.fft.fftfreq(M, d=pixel)
+    k2 = k[:, None] ** 2 + k[None, :] ** 2
+    return np.exp(-1j * math.pi * wavelength * dz * k2)
+
+
+def _window(obj_slice: np.ndarray, y0: int, x0: int, M: int) -> np.ndarray:
+    if y0 < 0 or x0 < 0 or y0 + M > obj_slice.shape[0] or x0 + M > obj_slice.shape[1]:
+        raise ValueError(f"window ({y0},{x0})+{M} outside object {obj_slice.shape}")
+    return obj_slice[y0:y0 + M, x0:x0 + M]
+
+
+# ---------------------------------------------------------------------------
+# Multislice forward model G(p_i, V) (Section II-B).
+# ---------------------------------------------------------------------------
+def exit_waves(obj: np.ndarray, probe: np.ndarray, y0: int, x0: int, H: np.ndarray
+               ) -> Tuple[List[np.ndarray], np.ndarray]:
+    """Incident waves psi_0..psi_{S-1} at each slice and the far field Psi for one window.
+
+    psi_0 is the probe; phi_s = psi_s * t_s[window]; psi_{s+1} = F^-1(H F(phi_s));
+    Psi = F(phi_{S-1}).
+    """
+    M = probe.shape[0]
+    S = obj.shape[0]
+    psi = np.asarray(probe, dtype=np.complex128)
+    incident = []
+    phi = None
+    for s in range(S):
+        incident.append(psi)
+        phi = psi * _window(obj[s], y0, x0, M)
+        if s < S - 1:
+            psi = np.fft.ifft2(H * np.fft.fft2(phi))
+    far_field = np.fft.fft2(phi)
+    return incident, far_field
+
+
+def forward(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, H: np.ndarray) -> np.ndarray:
+    """Simulated intensities |G(p_i, V)|^2 for every position, float64 [n, M, M]."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    M = probe.shape[0]
+    out = np.empty((len(pos), M, M), dtype=np.float64)
+    for i, (y0, x0) in enumerate(np.asarray(pos)):
+        _, far = exit_waves(obj, probe, int(y0), int(x0), H)
+        out[i] = np.abs(far) ** 2
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Amplitude cost f_i (Eq. 1) and its gradient (Eq. 2) for one position.
+# ---------------------------------------------------------------------------
+def position_loss_and_patch_gradients(obj: np.ndarray, probe: np.ndarray, y0: int, x0: int,
+                                      meas: np.ndarray, H: np.ndarray) -> Tuple[float, np.ndarray]:
+    """f_i and the S window-sized pieces of df_i/dt (complex128 [S, M, M]).
+
+    With u = Psi/|Psi| (u = 0 where |Psi| = 0) and a = sqrt(meas):
+      dF/dPsi* direction g = 2 (|Psi| - a) u,
+      chi_{S-1} = F^H g = M^2 F^-1 g,
+      grad_s = chi_s * conj(psi_s),
+      chi_{s-1} = F^-1(conj(H) F(chi_s * conj(t_s)))     (adjoint of the propagation step).
+    """
+    M = probe.shape[0]
+    S = obj.shape[0]
+    incident, far = exit_waves(obj, probe, y0, x0, H)
+    a = np.sqrt(np.asarray(meas, dtype=np.float64))
+    mod = np.abs(far)
+    loss = float(np.sum((mod - a) ** 2))
+    u = np.zeros_like(far)
+    nz = mod > 0
+    u[nz] = far[nz] / mod[nz]
+    g_far = 2.0 * (mod - a) * u
+    chi = (M * M) * np.fft.ifft2(g_far)
+    grads = np.empty((S, M, M), dtype=np.complex128)
+    for s in range(S - 1, -1, -1):
+        grads[s] = chi * np.conj(incident[s])
+        if s > 0:
+            t_s = _window(obj[s], y0, x0, M)
+            chi = np.fft.ifft2(np.conj(H) * np.fft.fft2(chi * np.conj(t_s)))
+    return loss, grads
+
+
+def loss_and_gradient(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray,
+                      H: np.ndarray) -> Tuple[float, np.ndarray, np.ndarray]:
+    """F(V) summed over positions in order, per-position f_i, and dF/dt (complex128 like obj)."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    M = probe.shape[0]
+    grad = np.zeros_like(obj)
+    per_pos = np.empty(len(pos), dtype=np.float64)
+    total = 0.0
+    for i, (y0, x0) in enumerate(np.asarray(pos)):
+        y0, x0 = int(y0), int(x0)
+        f_i, patches = position_loss_and_patch_gradients(obj, probe, y0, x0, meas[i], H)
+        per_pos[i] = f_i
+        total += f_i
+        grad[:, y0:y0 + M, x0:x0 + M] += patches
+    return total, per_pos, grad
+
+
+# ---------------------------------------------------------------------------
+# Gradient decomposition into tiles with halos (Section III).
+# Reading: tiles are an even split of the object; a position belongs to the
+# tile that contains its window centre; the extended box is the tile grown by
+# the halo on every side and clipped to the object.
+# ---------------------------------------------------------------------------
+def tile_bounds(extent: int, count: int) -> List[int]:
+    """Tile edges along one axis: edge_k = floor(k * extent / count), k = 0..count."""
+    return [(k * extent) // count for k in range(count + 1)]
+
+
+def bin_positions(pos: np.ndarray, Hobj: int, Wobj: int, M: int, tiles_y: int, tiles_x: int) -> np.ndarray:
+    """Tile index (row-major) of every position, by the tile holding its window centre."""
+    ey = tile_bounds(Hobj, tiles_y)
+    ex = tile_bounds(Wobj, tiles_x)
+    out = np.empty(len(pos), dtype=np.int32)
+    for i, (y0, x0) in enumerate(np.asarray(pos)):
+        cy = int(y0) + M // 2
+        cx = int(x0) + M // 2
+        ty = 0
+        while ty + 1 < tiles_y and ey[ty + 1] <= cy:
+            ty += 1
+        tx = 0
+        while tx + 1 < tiles_x and ex[tx + 1] <= cx:
+            tx += 1
+        out[i] = ty * tiles_x + tx
+    return out
+
+
+def extended_box(Hobj: int, Wobj: int, tiles_y: int, tiles_x: int, ty: int, tx: int, halo: int
+                 ) -> Tuple[int, int, int, int]:
+    """(ey0, ey1, ex0, ex1): tile (ty, tx) grown by the halo, clipped to the object (half-open)."""
+    ey = tile_bounds(Hobj, tiles_y)
+    ex = tile_bounds(Wobj, tiles_x)
+    return (max(ey[ty] - halo, 0), min(ey[ty + 1] + halo, Hobj),
+            max(ex[tx] - halo, 0), min(ex[tx + 1] + halo, Wobj))
+
+
+def tile_gradient(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray, H: np.ndarray,
+                  tiles: Tuple[int, int], halo: int, ty: int, tx: int) -> Dict[str, object]:
+    """Loss and gradient of one tile's own positions, held on the tile's extended box."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    S, Hobj, Wobj = obj.shape
+    M = probe.shape[0]
+    tiles_y, tiles_x = tiles
+    owner = bin_positions(pos, Hobj, Wobj, M, tiles_y, tiles_x)
+    ey0, ey1, ex0, ex1 = extended_box(Hobj, Wobj, tiles_y, tiles_x, ty, tx, halo)
+    box = np.zeros((S, ey1 - ey0, ex1 - ex0), dtype=np.complex128)
+    loss = 0.0
+    mine = np.nonzero(owner == ty * tiles_x + tx)[0]
+    for i in mine:
+        y0, x0 = int(pos[i][0]), int(pos[i][1])
+        if y0 < ey0 or x0 < ex0 or y0 + M > ey1 or x0 + M > ex1:
+            raise ValueError(f"window of position {i} leaves the extended tile: halo too small")
+        f_i, patches = position_loss_and_patch_gradients(obj, probe, y0, x0, meas[i], H)
+        loss += f_i
+        box[:, y0 - ey0:y0 - ey0 + M, x0 - ex0:x0 - ex0 + M] += patches
+    return {"box": (ey0, ey1, ex0, ex1), "grad": box, "loss": loss, "positions": mine}
+
+
+def stitch_tile_gradients(shape: Sequence[int], tile_results: Sequence[Dict[str, object]]) -> np.ndarray:
+    """Sum of the tile gradients embedded at their extended boxes (overlaps add)."""
+    out = np.zeros(tuple(shape), dtype=np.complex128)
+    for r in tile_results:
+        ey0, ey1, ex0, ex1 = r["box"]
+        out[:, ey0:ey1, ex0:ex1] += r["grad"]
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Full-batch gradient descent on the slice transmissions.
+# Reading: the paper gives no step length; alpha = 1 / (2 M^2 max_r sum_i |P(r - r_i)|^2)
+# (the inverse of the largest diagonal of the single-slice Gauss-Newton
+# curvature of the amplitude cost, a conventional safe step).
+# ---------------------------------------------------------------------------
+def gd_step_size(probe: np.ndarray, pos: np.ndarray, Hobj: int, Wobj: int) -> float:
+    M = probe.shape[0]
+    cover = np.zeros((Hobj, Wobj), dtype=np.float64)
+    p2 = np.abs(probe) ** 2
+    for y0, x0 in np.asarray(pos):
+        cover[int(y0):int(y0) + M, int(x0):int(x0) + M] += p2
+    return 1.0 / (2.0 * M * M * float(cover.max()))
+
+
+def gd_step(obj: np.ndarray, grad: np.ndarray, alpha: float) -> np.ndarray:
+    return obj - alpha * grad
