@@ -1,0 +1,180 @@
+/*
+ * ptycho.h -- C ABI of the MI355X (gfx950) multislice ptychography hot path.
+ *
+ * Problem (Wang et al., "Image Gradient Decomposition for Parallel and
+ * Memory-Efficient Ptychographic Reconstruction", SC22):
+ *   Section II-B, Eq. 1:  F(V) = sum_i ( |y_i| - |G(p_i, V)| )^2
+ *   Section II-B (text after Eq. 1): G runs, slice after slice, a Fourier
+ *       transform and an inverse Fourier transform; each slice's output is the
+ *       next slice's input; the detector compares magnitudes of the far field.
+ *   Section III, Eq. 2: dF/dV = sum_i df_i/dV, each term non-zero only inside
+ *       the window of probe location i, so per-position gradients are
+ *       scatter-added into the image gradient.
+ *   Section III (tiles + halos): the image gradient and the probe locations
+ *       are divided into tiles; each tile is extended by a halo that covers its
+ *       probe windows; tile gradients of overlapping regions are added.
+ *
+ * Model computed by this library (per position i with window top-left (y0, x0)):
+ *   psi_0 = probe;  phi_s = psi_s * t_s[y0:y0+M, x0:x0+M]
+ *   psi_{s+1} = IDFT( H * DFT(phi_s) ),  H[ky,kx] = exp(-i pi lambda dz (ky^2+kx^2)),
+ *               k = fftfreq(M, d = pixel)           (s = 0 .. S-2)
+ *   Psi = DFT(phi_{S-1});  I = |Psi|^2   (unnormalised DFT, DC at [0,0], no shift)
+ *   f_i = sum_q ( |Psi| - sqrt(meas) )^2
+ *   grad = dF/dRe(t) + i dF/dIm(t)      (complex gradient w.r.t. the transmissions)
+ *
+ * Data types and layouts (all arrays are DEVICE pointers unless marked host):
+ *   complex values are interleaved float pairs (re, im) = "float2" below.
+ *   object:    slices of complex64, element (s, y, x) at obj[s*slice_stride + y*ld + x]
+ *   probe:     complex64 [M][M], row-major
+ *   positions: int32 [n][2] = (y0, x0) window top-left corners, in the object's
+ *              coordinates (global object coordinates for ptycho_tile_grad)
+ *   intensities / measurements: float32 [n][M][M], detector order as above
+ *   gradient:  complex64 with its own (slice_stride, ld)
+ *
+ * Ownership: the caller allocates and frees every array; the library keeps no
+ * pointer beyond the call's stream work.  A context owns its device tables and
+ * its workspace (allocated in ptycho_create / ptycho_reserve only), so the hot
+ * calls allocate nothing and are stream-ordered and asynchronous.
+ *
+ * Errors: every call returns PTYCHO_OK (0) or a negative code; a call that
+ * fails host validation enqueues nothing.  ptycho_last_error() returns a
+ * thread-local message for the last failure.  Windows that leave the object,
+ * the extended tile or the tile (conditions only visible on the device because
+ * positions live in device memory) are skipped by the kernels without any
+ * memory access and recorded in a device status word; ptycho_check()
+ * synchronises the context stream and reports it.
+ *
+ * Thread safety: one context must not be used by several host threads at once.
+ */
+#ifndef PTYCHO_H
+#define PTYCHO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ptycho_ctx ptycho_ctx;
+
+enum {
+  PTYCHO_OK = 0,
+  PTYCHO_E_ARG = -1,          /* null pointer, negative size, bad flag */
+  PTYCHO_E_SHAPE = -2,        /* inconsistent sizes or strides */
+  PTYCHO_E_BOUNDS = -3,       /* a window leaves the object */
+  PTYCHO_E_HALO = -4,         /* a window leaves the extended tile (halo too small) */
+  PTYCHO_E_ASSIGN = -5,       /* a window centre lies outside its tile */
+  PTYCHO_E_UNSUPPORTED = -6,  /* unsupported window size or slice count */
+  PTYCHO_E_HIP = -7,          /* HIP runtime error */
+  PTYCHO_E_NOMEM = -8,        /* device allocation failed (create/reserve only) */
+  PTYCHO_E_CAPACITY = -9      /* more positions than the context reserved */
+};
+
+/* flags for ptycho_loss_grad / ptycho_tile_grad */
+#define PTYCHO_ACCUMULATE 1u   /* add into grad and *loss instead of overwriting them */
+
+/* Status bits reported by ptycho_check (device status word). */
+#define PTYCHO_STATUS_BOUNDS 1u
+#define PTYCHO_STATUS_HALO 2u
+#define PTYCHO_STATUS_ASSIGN 4u
+
+/*
+ * ptycho_create: a context for windows of M x M pixels (M in {64, 128}) and
+ * S >= 1 slices (S <= 64), with the Fresnel propagator of one slice thickness
+ * dz_A for electrons of wavelength wavelength_A on pixels of pixel_A (all in
+ * Angstrom).  The FP32 DFT twiddles and the separable propagator factors are
+ * computed in FP64 on the host and rounded once.  `stream` is a hipStream_t
+ * (NULL = default stream) on which every later call of this context runs.
+ * max_positions bounds n of a single loss/gradient call (the per-position
+ * gradient staging lives in the context); 0 picks a default of 4096.
+ * Returns PTYCHO_E_UNSUPPORTED for other M or S, PTYCHO_E_NOMEM if the
+ * workspace cannot be allocated.
+ */
+int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, double dz_A,
+                  double pixel_A, int32_t max_positions, void* stream);
+int ptycho_destroy(ptycho_ctx* ctx);
+int ptycho_set_stream(ptycho_ctx* ctx, void* stream);
+/* Grow the context's per-call position capacity (allocates; not for hot loops). */
+int ptycho_reserve(ptycho_ctx* ctx, int32_t max_positions);
+/* Device bytes owned by the context (tables + workspace). */
+int64_t ptycho_workspace_bytes(const ptycho_ctx* ctx);
+
+/*
+ * ptycho_forward: simulated far-field intensities I_i = |G(p_i, V)|^2
+ * (Section II-B) for n positions; writes intens[n][M][M] (overwritten).
+ * obj has H x W pixels per slice with the given strides (ld >= W,
+ * slice_stride >= H*ld).  Windows outside [0,H)x[0,W) are skipped (their
+ * intensities are left untouched) and flagged PTYCHO_STATUS_BOUNDS.
+ * n == 0 is a no-op.
+ */
+int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                   int32_t ld, const void* probe, const int32_t* pos, int32_t n, float* intens);
+
+/*
+ * ptycho_loss_grad: amplitude cost F (Eq. 1) and its gradient (Eq. 2).
+ *   loss:         device double scalar; set to F (or F added when ACCUMULATE)
+ *   loss_per_pos: nullable device double [n]; f_i per position (overwritten)
+ *   grad:         device complex64 with (grad_slice_stride, grad_ld) over the
+ *                 same H x W x S extent as obj; set to dF/dRe t + i dF/dIm t
+ *                 (or added into it when ACCUMULATE).  It must not alias obj.
+ *   meas:         measured intensities float32 [n][M][M] (non-negative).
+ * Where |Psi| = 0 the direction Psi/|Psi| is taken as 0.
+ * n must not exceed the context's reserved capacity (PTYCHO_E_CAPACITY).
+ */
+int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                     int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                     double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride,
+                     int32_t grad_ld, uint32_t flags);
+
+/*
+ * ptycho_tile_grad: the gradient of one tile (Section III): the summed
+ * gradient of the positions assigned to tile [ty0,ty1) x [tx0,tx1) (global
+ * object pixels, half-open), held on its extended box
+ * [ey0, ey0+eh) x [ex0, ex0+ew), which must equal the tile grown by `halo`
+ * and clipped to the H x W object (else PTYCHO_E_SHAPE).
+ *   obj_ext:   the extended box of the object: element (s, y, x) of the box
+ *              (box-local y, x) at obj_ext[s*slice_stride + y*ld + x]; it may
+ *              be a view into the full object.
+ *   pos:       this tile's positions in GLOBAL object coordinates.
+ *   tile_grad: complex64 [S][eh][ew] (dense, box-local), overwritten unless
+ *              ACCUMULATE.
+ * Device-side checks: a window leaving the box is skipped and flagged
+ * PTYCHO_STATUS_HALO; a window whose centre (y0+M/2, x0+M/2) is outside the
+ * tile is skipped and flagged PTYCHO_STATUS_ASSIGN.
+ * Summing the tile gradients of all tiles (embedded at their boxes) gives the
+ * undecomposed gradient.
+ */
+int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t ex0, int32_t eh,
+                     int32_t ew, int64_t slice_stride, int32_t ld, int32_t ty0, int32_t ty1, int32_t tx0,
+                     int32_t tx1, int32_t halo, int32_t H, int32_t W, const void* probe,
+                     const int32_t* pos, int32_t n, const float* meas, double* loss,
+                     double* loss_per_pos, void* tile_grad, uint32_t flags);
+
+/*
+ * Host helpers (host pointers).
+ * ptycho_bin_positions: tile index (row-major, tiles_y x tiles_x even split,
+ * edge_k = floor(k*extent/count)) of every position: the tile containing the
+ * window centre (y0 + M/2, x0 + M/2).  Returns PTYCHO_E_BOUNDS if a window
+ * leaves the object.
+ * ptycho_validate_positions: PTYCHO_OK iff every window lies inside H x W.
+ * ptycho_tile_box: the extended box of tile (ty, tx) for a halo.
+ */
+int ptycho_bin_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t W, int32_t M,
+                         int32_t tiles_y, int32_t tiles_x, int32_t* host_tile_of_pos);
+int ptycho_validate_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t W, int32_t M);
+int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int32_t ty, int32_t tx,
+                    int32_t halo, int32_t* ty0, int32_t* ty1, int32_t* tx0, int32_t* tx1, int32_t* ey0,
+                    int32_t* ey1, int32_t* ex0, int32_t* ex1);
+
+/* Synchronise the context stream; PTYCHO_OK, or the first HIP error, or a
+ * negative code for the device status word (which is then cleared). */
+int ptycho_check(ptycho_ctx* ctx, uint32_t* status_out);
+
+const char* ptycho_last_error(void);
+const char* ptycho_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTYCHO_H */

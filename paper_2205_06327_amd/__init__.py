@@ -1,0 +1,17 @@
+"""MI355X-native hot path of gradient-decomposed multislice ptychography.
+
+The work is done by the HIP library ``libptycho.so`` (include/ptycho.h);
+this package is its Python binding plus the host-side tile scheduler.
+"""
+from ._binding import (  # noqa: F401
+    Context,
+    PtychoError,
+    bin_positions,
+    lib,
+    ptycho_forward,
+    ptycho_loss_grad,
+    ptycho_tile_grad,
+    tile_box,
+    validate_positions,
+    version,
+)

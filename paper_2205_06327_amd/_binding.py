@@ -1,0 +1,283 @@
+"""Thin ctypes binding of libptycho.so (include/ptycho.h).
+
+Only argument marshalling lives here: tensors are turned into raw device
+pointers and strides, and every computation runs in the HIP library.  The
+library must be built (``python -m paper_2205_06327_amd.build``); if it is
+missing, every call raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libptycho.so")
+
+PTYCHO_OK = 0
+PTYCHO_ACCUMULATE = 1
+ERRORS = {
+    -1: "PTYCHO_E_ARG",
+    -2: "PTYCHO_E_SHAPE",
+    -3: "PTYCHO_E_BOUNDS",
+    -4: "PTYCHO_E_HALO",
+    -5: "PTYCHO_E_ASSIGN",
+    -6: "PTYCHO_E_UNSUPPORTED",
+    -7: "PTYCHO_E_HIP",
+    -8: "PTYCHO_E_NOMEM",
+    -9: "PTYCHO_E_CAPACITY",
+}
+EXPORTED = (
+    "ptycho_create", "ptycho_destroy", "ptycho_set_stream", "ptycho_reserve", "ptycho_workspace_bytes",
+    "ptycho_forward", "ptycho_loss_grad", "ptycho_tile_grad", "ptycho_bin_positions",
+    "ptycho_validate_positions", "ptycho_tile_box", "ptycho_check", "ptycho_last_error", "ptycho_version",
+)
+
+
+class PtychoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = ERRORS.get(code, str(code))
+
+
+_lib = None
+
+c_i32, c_i64, c_u32, c_dbl, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double, ctypes.c_void_p
+P_i32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2205_06327_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "ptycho_create": (ctypes.c_int, [ctypes.POINTER(c_vp), c_i32, c_i32, c_dbl, c_dbl, c_dbl, c_i32, c_vp]),
+            "ptycho_destroy": (ctypes.c_int, [c_vp]),
+            "ptycho_set_stream": (ctypes.c_int, [c_vp, c_vp]),
+            "ptycho_reserve": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_workspace_bytes": (c_i64, [c_vp]),
+            "ptycho_forward": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp]),
+            "ptycho_loss_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
+                                                c_vp, c_vp, c_vp, c_i64, c_i32, c_u32]),
+            "ptycho_tile_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32,
+                                                c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp,
+                                                c_vp, c_vp, c_u32]),
+            "ptycho_bin_positions": (ctypes.c_int, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32]),
+            "ptycho_validate_positions": (ctypes.c_int, [P_i32, c_i32, c_i32, c_i32, c_i32]),
+            "ptycho_tile_box": (ctypes.c_int, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32] + [P_i32] * 8),
+            "ptycho_check": (ctypes.c_int, [c_vp, ctypes.POINTER(c_u32)]),
+            "ptycho_last_error": (ctypes.c_char_p, []),
+            "ptycho_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != PTYCHO_OK:
+        raise PtychoError(rc, lib().ptycho_last_error().decode())
+
+
+def version() -> str:
+    return lib().ptycho_version().decode()
+
+
+# ---------------------------------------------------------------------------
+# host helpers (numpy int32 [n, 2])
+# ---------------------------------------------------------------------------
+def _pos_np(pos) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(pos, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+def validate_positions(pos, H: int, W: int, M: int) -> None:
+    a = _pos_np(pos)
+    _check(lib().ptycho_validate_positions(a.ctypes.data_as(P_i32), len(a), H, W, M))
+
+
+def bin_positions(pos, H: int, W: int, M: int, tiles_y: int, tiles_x: int) -> np.ndarray:
+    a = _pos_np(pos)
+    out = np.empty(len(a), dtype=np.int32)
+    _check(lib().ptycho_bin_positions(a.ctypes.data_as(P_i32), len(a), H, W, M, tiles_y, tiles_x,
+                                      out.ctypes.data_as(P_i32)))
+    return out
+
+
+def tile_box(H: int, W: int, tiles_y: int, tiles_x: int, ty: int, tx: int, halo: int):
+    """((ty0, ty1, tx0, tx1), (ey0, ey1, ex0, ex1)) of tile (ty, tx)."""
+    v = [ctypes.c_int32() for _ in range(8)]
+    _check(lib().ptycho_tile_box(H, W, tiles_y, tiles_x, ty, tx, halo, *[ctypes.byref(x) for x in v]))
+    vals = [x.value for x in v]
+    return tuple(vals[:4]), tuple(vals[4:])
+
+
+# ---------------------------------------------------------------------------
+# device calls (torch tensors on the GPU)
+# ---------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr() -> int:
+    torch = _torch()
+    return int(torch.cuda.current_stream().cuda_stream)
+
+
+def _obj_geometry(obj) -> Tuple[int, int, int, int, int]:
+    """(S, H, W, slice_stride, ld) of a complex64 [S, H, W] tensor with unit column stride."""
+    torch = _torch()
+    if obj.dtype != torch.complex64 or obj.dim() != 3 or obj.stride(2) != 1:
+        raise ValueError("object must be complex64 [S, H, W] with unit stride along W")
+    S, H, W = obj.shape
+    return S, H, W, obj.stride(0), obj.stride(1)
+
+
+def _need(t, dtype, shape=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+class Context:
+    """A library context for M x M windows and S slices (one per stream of work)."""
+
+    def __init__(self, M: int, S: int, wavelength_A: float, dz_A: float, pixel_A: float,
+                 max_positions: int = 0):
+        self._h = c_vp()
+        self.M, self.S = int(M), int(S)
+        _check(lib().ptycho_create(ctypes.byref(self._h), self.M, self.S, float(wavelength_A), float(dz_A),
+                                   float(pixel_A), int(max_positions), c_vp(_stream_ptr())))
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise RuntimeError("context destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            lib().ptycho_destroy(self._h)
+            self._h = c_vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self) -> None:
+        _check(lib().ptycho_set_stream(self.handle, c_vp(_stream_ptr())))
+
+    def reserve(self, max_positions: int) -> None:
+        _check(lib().ptycho_reserve(self.handle, int(max_positions)))
+
+    def workspace_bytes(self) -> int:
+        return int(lib().ptycho_workspace_bytes(self.handle))
+
+    def check(self) -> int:
+        st = c_u32()
+        _check(lib().ptycho_check(self.handle, ctypes.byref(st)))
+        return st.value
+
+
+def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
+    """I_i = |G(p_i, V)|^2 for every position; returns float32 [n, M, M]."""
+    torch = _torch()
+    S, H, W, ss, ld = _obj_geometry(obj)
+    if S != ctx.S:
+        raise ValueError(f"object has {S} slices, context {ctx.S}")
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(pos, torch.int32, None, "pos")
+    n = pos.shape[0]
+    if intens is None:
+        intens = torch.empty((n, M, M), dtype=torch.float32, device=obj.device)
+    _need(intens, torch.float32, (n, M, M), "intens")
+    ctx._bind_stream()
+    _check(lib().ptycho_forward(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                c_vp(pos.data_ptr()), n, c_vp(intens.data_ptr())))
+    return intens
+
+
+def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, loss_per_pos=None,
+                     accumulate: bool = False):
+    """(loss float64 [1], grad complex64 [S, H, W]) of the amplitude cost."""
+    torch = _torch()
+    S, H, W, ss, ld = _obj_geometry(obj)
+    if S != ctx.S:
+        raise ValueError(f"object has {S} slices, context {ctx.S}")
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(pos, torch.int32, None, "pos")
+    n = pos.shape[0]
+    _need(meas, torch.float32, (n, M, M), "meas")
+    if grad is None:
+        grad = torch.empty((S, H, W), dtype=torch.complex64, device=obj.device)
+    if grad.dtype != torch.complex64 or grad.dim() != 3 or tuple(grad.shape) != (S, H, W) or grad.stride(2) != 1:
+        raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=obj.device)
+    _need(loss, torch.float64, (1,), "loss")
+    lpp = c_vp(0)
+    if loss_per_pos is not None:
+        _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
+        lpp = c_vp(loss_per_pos.data_ptr())
+    ctx._bind_stream()
+    _check(lib().ptycho_loss_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                  c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
+                                  c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
+                                  PTYCHO_ACCUMULATE if accumulate else 0))
+    return loss, grad
+
+
+def ptycho_tile_grad(ctx: Context, obj_ext, box, tile, halo: int, H: int, W: int, probe, pos, meas,
+                     tile_grad=None, loss=None, loss_per_pos=None, accumulate: bool = False):
+    """Gradient of one tile's positions on its extended box.
+
+    box = (ey0, ex0, eh, ew); tile = (ty0, ty1, tx0, tx1) in global pixels;
+    obj_ext is the [S, eh, ew] box of the object (may be a view of the full object).
+    """
+    torch = _torch()
+    S, eh, ew, ss, ld = _obj_geometry(obj_ext)
+    ey0, ex0, beh, bew = box
+    if (beh, bew) != (eh, ew) or S != ctx.S:
+        raise ValueError("obj_ext shape does not match the box or the context")
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(pos, torch.int32, None, "pos")
+    n = pos.shape[0]
+    _need(meas, torch.float32, (n, M, M), "meas")
+    if tile_grad is None:
+        tile_grad = torch.empty((S, eh, ew), dtype=torch.complex64, device=obj_ext.device)
+    _need(tile_grad, torch.complex64, (S, eh, ew), "tile_grad")
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=obj_ext.device)
+    _need(loss, torch.float64, (1,), "loss")
+    lpp = c_vp(0)
+    if loss_per_pos is not None:
+        _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
+        lpp = c_vp(loss_per_pos.data_ptr())
+    ty0, ty1, tx0, tx1 = tile
+    ctx._bind_stream()
+    _check(lib().ptycho_tile_grad(ctx.handle, c_vp(obj_ext.data_ptr()), ey0, ex0, eh, ew, ss, ld, ty0, ty1, tx0,
+                                  tx1, halo, H, W, c_vp(probe.data_ptr()), c_vp(pos.data_ptr()), n,
+                                  c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp, c_vp(tile_grad.data_ptr()),
+                                  PTYCHO_ACCUMULATE if accumulate else 0))
+    return loss, tile_grad

@@ -1,0 +1,381 @@
+// ptycho_api.cpp -- C ABI of the multislice ptychography library: contexts,
+// FP64-built tables, host validation, tile binning and the stream-ordered
+// launches of the fused kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ptycho.h"
+#include "ptycho_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(PTYCHO_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PT_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+// fftfreq(M, d)[k]: k/(M d) for k < M/2, (k - M)/(M d) otherwise (M even).
+double fft_freq(int k, int M, double d) { return (k < M / 2 ? k : k - M) / (M * d); }
+
+}  // namespace
+
+struct ptycho_ctx {
+  int M = 0, S = 0;
+  double wavelength = 0, dz = 0, pixel = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int grid = 0;            // persistent workgroups of the fused kernels
+  int capacity = 0;        // positions per call
+  float2* d_tw = nullptr;  // W_M^e
+  float2* d_h = nullptr;   // separable propagator factor
+  float2* d_ws = nullptr;  // incident-wave store, grid * (S-1) * M*M
+  double* d_loss = nullptr;  // per-position losses [capacity]
+  unsigned* d_status = nullptr;
+  int64_t bytes = 0;
+};
+
+namespace {
+
+void free_ctx(ptycho_ctx* c) {
+  if (!c) return;
+  if (c->d_tw) (void)hipFree(c->d_tw);
+  if (c->d_h) (void)hipFree(c->d_h);
+  if (c->d_ws) (void)hipFree(c->d_ws);
+  if (c->d_loss) (void)hipFree(c->d_loss);
+  if (c->d_status) (void)hipFree(c->d_status);
+  delete c;
+}
+
+int validate_windows_host(const int32_t* pos, int32_t n, int32_t H, int32_t W, int32_t M) {
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t y0 = pos[2 * i], x0 = pos[2 * i + 1];
+    if (y0 < 0 || x0 < 0 || static_cast<int64_t>(y0) + M > H || static_cast<int64_t>(x0) + M > W)
+      return fail(PTYCHO_E_BOUNDS, "position %d: window (%d,%d)+%d leaves the %dx%d object", i, y0, x0, M, H, W);
+  }
+  return PTYCHO_OK;
+}
+
+int check_object_args(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const void* probe, const int32_t* pos, int32_t n) {
+  if (!c) return fail(PTYCHO_E_ARG, "null context");
+  if (n < 0) return fail(PTYCHO_E_ARG, "negative position count");
+  if (n > 0 && (!obj || !probe || !pos)) return fail(PTYCHO_E_ARG, "null object, probe or positions");
+  if (H < c->M || W < c->M) return fail(PTYCHO_E_SHAPE, "object %dx%d smaller than the %d window", H, W, c->M);
+  if (ld < W) return fail(PTYCHO_E_SHAPE, "ld %d < W %d", ld, W);
+  if (slice_stride < static_cast<int64_t>(H) * ld && c->S > 1)
+    return fail(PTYCHO_E_SHAPE, "slice stride %lld < H*ld", static_cast<long long>(slice_stride));
+  if (static_cast<int64_t>(ld) * c->M >= (int64_t(1) << 31))
+    return fail(PTYCHO_E_SHAPE, "row stride %d too large for a window", ld);
+  return PTYCHO_OK;
+}
+
+ptycho::KernelArgs base_args(const ptycho_ctx* c) {
+  ptycho::KernelArgs a{};
+  a.M = c->M;
+  a.S = c->S;
+  a.tw = c->d_tw;
+  a.h = c->d_h;
+  a.ws = c->d_ws;
+  a.loss_work = c->d_loss;
+  a.status = c->d_status;
+  return a;
+}
+
+int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, double* loss, uint32_t flags) {
+  const bool acc = (flags & PTYCHO_ACCUMULATE) != 0;
+  if (!acc) PT_HIP(ptycho::launch_zero_slices(a.grad, c->S, gh, gw, a.gslice, a.gld, c->stream));
+  if (a.n > 0) {
+    const int grid = a.n < c->grid ? a.n : c->grid;
+    PT_HIP(ptycho::launch_fused(a, true, grid, c->stream));
+  }
+  PT_HIP(ptycho::launch_finalize_loss(c->d_loss, a.n, loss, acc, c->stream));
+  return PTYCHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ptycho_last_error(void) { return g_err.c_str(); }
+const char* ptycho_version(void) { return "ptycho-mi355x 0.1 (gfx950)"; }
+
+int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, double dz_A, double pixel_A,
+                  int32_t max_positions, void* stream) {
+  if (!out) return fail(PTYCHO_E_ARG, "null output pointer");
+  *out = nullptr;
+  if (M != 64 && M != 128) return fail(PTYCHO_E_UNSUPPORTED, "window size %d not supported (64 or 128)", M);
+  if (S < 1 || S > 64) return fail(PTYCHO_E_UNSUPPORTED, "slice count %d not supported (1..64)", S);
+  if (!(pixel_A > 0) || !std::isfinite(wavelength_A) || !std::isfinite(dz_A))
+    return fail(PTYCHO_E_ARG, "invalid physics (wavelength %g, dz %g, pixel %g)", wavelength_A, dz_A, pixel_A);
+  if (max_positions < 0) return fail(PTYCHO_E_ARG, "negative capacity");
+  ptycho_ctx* c = new ptycho_ctx();
+  c->M = M;
+  c->S = S;
+  c->wavelength = wavelength_A;
+  c->dz = dz_A;
+  c->pixel = pixel_A;
+  c->stream = static_cast<hipStream_t>(stream);
+  hipError_t e = hipGetDevice(&c->device);
+  int cus = 0;
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "device query");
+  }
+  c->grid = cus > 0 ? cus : 256;  // one workgroup per CU (LDS-bound occupancy)
+  c->capacity = max_positions > 0 ? max_positions : 4096;
+
+  // Tables computed in double precision, rounded once to float.
+  std::vector<float2> tw(M), h(M);
+  for (int e2 = 0; e2 < M; ++e2) {
+    const double ang = -2.0 * kPi * e2 / M;
+    tw[e2] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+    const double f = fft_freq(e2, M, pixel_A);
+    const double ph = -kPi * wavelength_A * dz_A * f * f;
+    h[e2] = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
+  }
+  const size_t ws_elems = static_cast<size_t>(c->grid) * (S > 1 ? S - 1 : 0) * M * M;
+  if ((e = hipMalloc(&c->d_tw, M * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&c->d_h, M * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&c->d_loss, static_cast<size_t>(c->capacity) * sizeof(double))) != hipSuccess ||
+      (e = hipMalloc(&c->d_status, sizeof(unsigned))) != hipSuccess ||
+      (ws_elems > 0 && (e = hipMalloc(&c->d_ws, ws_elems * sizeof(float2))) != hipSuccess)) {
+    free_ctx(c);
+    return fail(PTYCHO_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  c->bytes = static_cast<int64_t>(2 * M * sizeof(float2) + c->capacity * sizeof(double) + sizeof(unsigned) +
+                                  ws_elems * sizeof(float2));
+  if ((e = hipMemcpy(c->d_tw, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_h, h.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->d_status, 0, sizeof(unsigned))) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
+    free_ctx(c);
+    return hip_fail(e, "table upload");
+  }
+  *out = c;
+  return PTYCHO_OK;
+}
+
+int ptycho_destroy(ptycho_ctx* ctx) {
+  if (!ctx) return PTYCHO_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+  return PTYCHO_OK;
+}
+
+int ptycho_set_stream(ptycho_ctx* ctx, void* stream) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  ctx->stream = static_cast<hipStream_t>(stream);
+  return PTYCHO_OK;
+}
+
+int ptycho_reserve(ptycho_ctx* ctx, int32_t max_positions) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (max_positions <= ctx->capacity) return PTYCHO_OK;
+  PT_HIP(hipStreamSynchronize(ctx->stream));
+  double* p = nullptr;
+  hipError_t e = hipMalloc(&p, static_cast<size_t>(max_positions) * sizeof(double));
+  if (e != hipSuccess) return fail(PTYCHO_E_NOMEM, "capacity %d: %s", max_positions, hipGetErrorString(e));
+  (void)hipFree(ctx->d_loss);
+  ctx->d_loss = p;
+  ctx->bytes += static_cast<int64_t>(max_positions - ctx->capacity) * static_cast<int64_t>(sizeof(double));
+  ctx->capacity = max_positions;
+  return PTYCHO_OK;
+}
+
+int64_t ptycho_workspace_bytes(const ptycho_ctx* ctx) { return ctx ? ctx->bytes : 0; }
+
+int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                   const void* probe, const int32_t* pos, int32_t n, float* intens) {
+  int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
+  if (rc != PTYCHO_OK) return rc;
+  if (n == 0) return PTYCHO_OK;
+  if (!intens) return fail(PTYCHO_E_ARG, "null intensity output");
+  ptycho::KernelArgs a = base_args(ctx);
+  a.n = n;
+  a.obj = static_cast<const float2*>(obj);
+  a.slice_stride = slice_stride;
+  a.ld = ld;
+  a.bh = H;
+  a.bw = W;
+  a.oob_flag = PTYCHO_STATUS_BOUNDS;
+  a.probe = static_cast<const float2*>(probe);
+  a.pos = pos;
+  a.intens = intens;
+  const int grid = n < ctx->grid ? n : ctx->grid;
+  PT_HIP(ptycho::launch_fused(a, false, grid, ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                     const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                     double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld, uint32_t flags) {
+  int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
+  if (rc != PTYCHO_OK) return rc;
+  if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
+  if (!loss || !grad) return fail(PTYCHO_E_ARG, "null loss or gradient");
+  if (n > 0 && !meas) return fail(PTYCHO_E_ARG, "null measurements");
+  if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
+    return fail(PTYCHO_E_SHAPE, "gradient strides do not cover %dx%d", H, W);
+  if (grad == obj) return fail(PTYCHO_E_ARG, "gradient aliases the object");
+  ptycho::KernelArgs a = base_args(ctx);
+  a.n = n;
+  a.obj = static_cast<const float2*>(obj);
+  a.slice_stride = slice_stride;
+  a.ld = ld;
+  a.bh = H;
+  a.bw = W;
+  a.oob_flag = PTYCHO_STATUS_BOUNDS;
+  a.probe = static_cast<const float2*>(probe);
+  a.pos = pos;
+  a.meas = meas;
+  a.loss_pos = loss_per_pos;
+  a.grad = static_cast<float2*>(grad);
+  a.gslice = grad_slice_stride;
+  a.gld = grad_ld;
+  return run_loss_grad(ctx, a, H, W, loss, flags);
+}
+
+int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int32_t ty, int32_t tx, int32_t halo,
+                    int32_t* ty0, int32_t* ty1, int32_t* tx0, int32_t* tx1, int32_t* ey0, int32_t* ey1, int32_t* ex0,
+                    int32_t* ex1) {
+  if (tiles_y < 1 || tiles_x < 1 || ty < 0 || tx < 0 || ty >= tiles_y || tx >= tiles_x || halo < 0 || H < 1 || W < 1)
+    return fail(PTYCHO_E_ARG, "bad tile grid request");
+  const int32_t a0 = static_cast<int32_t>(static_cast<int64_t>(ty) * H / tiles_y);
+  const int32_t a1 = static_cast<int32_t>(static_cast<int64_t>(ty + 1) * H / tiles_y);
+  const int32_t b0 = static_cast<int32_t>(static_cast<int64_t>(tx) * W / tiles_x);
+  const int32_t b1 = static_cast<int32_t>(static_cast<int64_t>(tx + 1) * W / tiles_x);
+  if (ty0) *ty0 = a0;
+  if (ty1) *ty1 = a1;
+  if (tx0) *tx0 = b0;
+  if (tx1) *tx1 = b1;
+  if (ey0) *ey0 = a0 - halo < 0 ? 0 : a0 - halo;
+  if (ey1) *ey1 = a1 + halo > H ? H : a1 + halo;
+  if (ex0) *ex0 = b0 - halo < 0 ? 0 : b0 - halo;
+  if (ex1) *ex1 = b1 + halo > W ? W : b1 + halo;
+  return PTYCHO_OK;
+}
+
+int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t ex0, int32_t eh, int32_t ew,
+                     int64_t slice_stride, int32_t ld, int32_t ty0, int32_t ty1, int32_t tx0, int32_t tx1,
+                     int32_t halo, int32_t H, int32_t W, const void* probe, const int32_t* pos, int32_t n,
+                     const float* meas, double* loss, double* loss_per_pos, void* tile_grad, uint32_t flags) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (n < 0) return fail(PTYCHO_E_ARG, "negative position count");
+  if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
+  if (!loss || !tile_grad || (n > 0 && (!obj_ext || !probe || !pos || !meas)))
+    return fail(PTYCHO_E_ARG, "null pointer argument");
+  if (halo < 0 || ty0 < 0 || tx0 < 0 || ty1 <= ty0 || tx1 <= tx0 || ty1 > H || tx1 > W)
+    return fail(PTYCHO_E_SHAPE, "bad tile [%d,%d)x[%d,%d) in %dx%d", ty0, ty1, tx0, tx1, H, W);
+  const int32_t wy0 = ty0 - halo < 0 ? 0 : ty0 - halo, wy1 = ty1 + halo > H ? H : ty1 + halo;
+  const int32_t wx0 = tx0 - halo < 0 ? 0 : tx0 - halo, wx1 = tx1 + halo > W ? W : tx1 + halo;
+  if (ey0 != wy0 || ex0 != wx0 || eh != wy1 - wy0 || ew != wx1 - wx0)
+    return fail(PTYCHO_E_SHAPE, "extended box (%d,%d)+(%d,%d) is not the tile grown by halo %d: expected (%d,%d)+(%d,%d)",
+                ey0, ex0, eh, ew, halo, wy0, wx0, wy1 - wy0, wx1 - wx0);
+  if (eh < ctx->M || ew < ctx->M) return fail(PTYCHO_E_HALO, "extended box smaller than a window");
+  if (ld < ew || (ctx->S > 1 && slice_stride < static_cast<int64_t>(eh) * ld))
+    return fail(PTYCHO_E_SHAPE, "object strides do not cover the extended box");
+  if (static_cast<int64_t>(ld) * ctx->M >= (int64_t(1) << 31)) return fail(PTYCHO_E_SHAPE, "row stride too large");
+  if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  ptycho::KernelArgs a = base_args(ctx);
+  a.n = n;
+  a.obj = static_cast<const float2*>(obj_ext);
+  a.slice_stride = slice_stride;
+  a.ld = ld;
+  a.bh = eh;
+  a.bw = ew;
+  a.oy = ey0;
+  a.ox = ex0;
+  a.check_tile = 1;
+  a.ty0 = ty0;
+  a.ty1 = ty1;
+  a.tx0 = tx0;
+  a.tx1 = tx1;
+  a.oob_flag = PTYCHO_STATUS_HALO;
+  a.probe = static_cast<const float2*>(probe);
+  a.pos = pos;
+  a.meas = meas;
+  a.loss_pos = loss_per_pos;
+  a.grad = static_cast<float2*>(tile_grad);
+  a.gslice = static_cast<long long>(eh) * ew;
+  a.gld = ew;
+  return run_loss_grad(ctx, a, eh, ew, loss, flags);
+}
+
+int ptycho_validate_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t W, int32_t M) {
+  if (n < 0 || (n > 0 && !host_pos)) return fail(PTYCHO_E_ARG, "bad position array");
+  if (M < 1 || H < 1 || W < 1) return fail(PTYCHO_E_ARG, "bad sizes");
+  return validate_windows_host(host_pos, n, H, W, M);
+}
+
+int ptycho_bin_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t W, int32_t M, int32_t tiles_y,
+                         int32_t tiles_x, int32_t* host_tile_of_pos) {
+  if (n < 0 || (n > 0 && (!host_pos || !host_tile_of_pos))) return fail(PTYCHO_E_ARG, "bad arrays");
+  if (tiles_y < 1 || tiles_x < 1 || M < 2 || H < 1 || W < 1) return fail(PTYCHO_E_ARG, "bad tile grid");
+  int rc = validate_windows_host(host_pos, n, H, W, M);
+  if (rc != PTYCHO_OK) return rc;
+  // Tile edges edge_k = floor(k*extent/count); the owner is the tile whose
+  // half-open span holds the window centre.
+  std::vector<int32_t> ey(tiles_y + 1), ex(tiles_x + 1);
+  for (int k = 0; k <= tiles_y; ++k) ey[k] = static_cast<int32_t>(static_cast<int64_t>(k) * H / tiles_y);
+  for (int k = 0; k <= tiles_x; ++k) ex[k] = static_cast<int32_t>(static_cast<int64_t>(k) * W / tiles_x);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t cy = host_pos[2 * i] + M / 2, cx = host_pos[2 * i + 1] + M / 2;
+    int32_t a = 0, b = tiles_y - 1;  // last edge <= cy
+    while (a < b) {
+      const int32_t mid = (a + b + 1) / 2;
+      if (ey[mid] <= cy) a = mid; else b = mid - 1;
+    }
+    int32_t c = 0, d = tiles_x - 1;
+    while (c < d) {
+      const int32_t mid = (c + d + 1) / 2;
+      if (ex[mid] <= cx) c = mid; else d = mid - 1;
+    }
+    host_tile_of_pos[i] = a * tiles_x + c;
+  }
+  return PTYCHO_OK;
+}
+
+int ptycho_check(ptycho_ctx* ctx, uint32_t* status_out) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  PT_HIP(hipStreamSynchronize(ctx->stream));
+  unsigned st = 0;
+  PT_HIP(hipMemcpy(&st, ctx->d_status, sizeof st, hipMemcpyDeviceToHost));
+  if (status_out) *status_out = st;
+  if (st) {
+    PT_HIP(ptycho::launch_clear_status(ctx->d_status, ctx->stream));
+    PT_HIP(hipStreamSynchronize(ctx->stream));
+    if (st & PTYCHO_STATUS_BOUNDS) return fail(PTYCHO_E_BOUNDS, "a window left the object (status 0x%x)", st);
+    if (st & PTYCHO_STATUS_HALO) return fail(PTYCHO_E_HALO, "a window left the extended tile (status 0x%x)", st);
+    return fail(PTYCHO_E_ASSIGN, "a window centre lay outside its tile (status 0x%x)", st);
+  }
+  return PTYCHO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+"""CPU checks of the C ABI: the library loads, exports what the header declares,
+and its host-side validation, binning and tile geometry agree with the oracle."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import ptycho_synth as ps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptycho.h")
+
+pt = pytest.importorskip("paper_2205_06327_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptycho_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_calls():
+    names = declared_functions()
+    for required in ("ptycho_forward", "ptycho_loss_grad", "ptycho_tile_grad", "ptycho_create", "ptycho_check"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pt.lib()
+    names = declared_functions()
+    out = subprocess.run(["nm", "-D", "--defined-only", pt._binding.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\bT\s+(ptycho_[a-z_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert isinstance(getattr(lib, n), ctypes._CFuncPtr)
+    assert set(pt._binding.EXPORTED) == set(names)
+
+
+def test_create_rejects_unsupported_shapes_before_touching_the_device():
+    lib = pt.lib()
+    h = ctypes.c_void_p()
+    assert lib.ptycho_create(ctypes.byref(h), 96, 4, 0.0197, 2.0, 0.1, 0, None) == -6
+    assert "window size" in lib.ptycho_last_error().decode()
+    assert lib.ptycho_create(ctypes.byref(h), 128, 0, 0.0197, 2.0, 0.1, 0, None) == -6
+    assert lib.ptycho_create(ctypes.byref(h), 128, 65, 0.0197, 2.0, 0.1, 0, None) == -6
+    assert lib.ptycho_create(ctypes.byref(h), 128, 4, 0.0197, 2.0, 0.0, 0, None) == -1
+    assert lib.ptycho_create(None, 128, 4, 0.0197, 2.0, 0.1, 0, None) == -1
+    assert not h.value
+
+
+def test_null_context_calls_fail_cleanly():
+    lib = pt.lib()
+    assert lib.ptycho_forward(None, None, 256, 256, 0, 256, None, None, 0, None) == -1
+    assert lib.ptycho_loss_grad(None, None, 256, 256, 0, 256, None, None, 0, None, None, None, None, 0, 256, 0) == -1
+    assert lib.ptycho_check(None, None) == -1
+    assert lib.ptycho_destroy(None) == 0
+
+
+def test_validate_positions():
+    pt.validate_positions([[0, 0], [192, 192]], 256, 256, 64)
+    with pytest.raises(pt.PtychoError) as e:
+        pt.validate_positions([[0, 0], [193, 0]], 256, 256, 64)
+    assert e.value.name == "PTYCHO_E_BOUNDS"
+    with pytest.raises(pt.PtychoError):
+        pt.validate_positions([[-1, 0]], 256, 256, 64)
+    pt.validate_positions(np.zeros((0, 2), np.int32), 256, 256, 64)
+
+
+@pytest.mark.parametrize("W,M,tiles,step,n_side", [(2048, 128, (4, 4), 14, (126, 132)), (1000, 64, (3, 5), 9, (40, 31)),
+                                                   (256, 64, (2, 2), 8, (16, 16))])
+def test_binning_matches_oracle(W, M, tiles, step, n_side):
+    pos = ps.raster_positions(W, M, n_side[0], n_side[1], step)
+    got = pt.bin_positions(pos, W, W, M, *tiles)
+    ref = oracle.bin_positions(pos, W, W, M, *tiles)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_binning_random_positions_matches_oracle():
+    rng = np.random.default_rng(0)
+    pos = np.stack([rng.integers(0, 700 - 64, 500), rng.integers(0, 611 - 64, 500)], axis=1).astype(np.int32)
+    np.testing.assert_array_equal(pt.bin_positions(pos, 700, 611, 64, 3, 7), oracle.bin_positions(pos, 700, 611, 64, 3, 7))
+
+
+def test_tile_box_matches_oracle():
+    for (H, W, ty_n, tx_n, halo) in [(2048, 2048, 4, 4, 64), (700, 611, 3, 7, 40), (256, 256, 1, 1, 10)]:
+        for ty in range(ty_n):
+            for tx in range(tx_n):
+                (t0, t1, u0, u1), box = pt.tile_box(H, W, ty_n, tx_n, ty, tx, halo)
+                assert box == oracle.extended_box(H, W, ty_n, tx_n, ty, tx, halo)
+                ey = oracle.tile_bounds(H, ty_n)
+                ex = oracle.tile_bounds(W, tx_n)
+                assert (t0, t1, u0, u1) == (ey[ty], ey[ty + 1], ex[tx], ex[tx + 1])

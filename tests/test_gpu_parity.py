@@ -1,0 +1,179 @@
+"""GPU (gfx950) vs FP64 oracle parity of the fused forward / loss / adjoint path.
+
+Tolerances: intensities 1e-5 relative L2, gradients 1e-4 relative L2, loss 1e-5
+relative (FP32 kernel against the FP64 oracle on identical inputs).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import ptycho_synth as ps
+from gpu_helpers import context, problem, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL_I, TOL_G, TOL_L = 1e-5, 1e-4, 1e-5
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2205_06327_amd as pt
+    pt.lib()
+    return torch
+
+
+def run_forward(spec, d, obj_key="obj_eval"):
+    import paper_2205_06327_amd as pt
+    import torch
+    t = to_dev(d, obj_key)
+    ctx = context(spec, max_positions=len(d["pos"]))
+    I = pt.ptycho_forward(ctx, t["obj"], t["probe"], t["pos"])
+    ctx.check()
+    torch.cuda.synchronize()
+    return I.cpu().numpy()
+
+
+def run_loss_grad(spec, d, obj_key="obj_eval"):
+    import paper_2205_06327_amd as pt
+    import torch
+    t = to_dev(d, obj_key)
+    n = len(d["pos"])
+    ctx = context(spec, max_positions=max(n, 1))
+    lpp = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    loss, grad = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], loss_per_pos=lpp)
+    ctx.check()
+    torch.cuda.synchronize()
+    return float(loss.item()), lpp.cpu().numpy(), grad.cpu().numpy()
+
+
+CASES = {
+    # name: spec
+    "2d-256-m64 full scan (256 positions, noise-free)": ps.workload("2d-256-m64"),
+    "2d-1024-m128 reduced to 256^2, 5x6 positions": ps.reduced(ps.workload("2d-1024-m128"), W=256, ny=5, nx=6),
+    "ms8-1024-m128 reduced to 256^2, 5x7 positions": ps.reduced(ps.workload("ms8-1024-m128"), W=256, ny=5, nx=7),
+    "m64 S=3 ragged 13 positions": ps.with_overrides(ps.workload("2d-256-m64"), W=160, S=3, ny=13, nx=1, step=7,
+                                                      strength=0.4, noise=True),
+    "m128 S=16 3x3 positions": ps.reduced(ps.workload("ms16-2048-m128-tiles4x4"), W=192, ny=3, nx=3, S=16),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_parity(torch_cuda, name):
+    spec = CASES[name]
+    say(f"forward parity: {name}")
+    d = problem(spec)
+    I = run_forward(spec, d)
+    I_ref = oracle.forward(d["obj_eval"], d["probe"], d["pos"], d["H"])
+    err = rel_l2(I, I_ref)
+    say(f"  intensities rel L2 = {err:.3e}")
+    assert err <= TOL_I
+    # Parseval on the pure-phase truth: every pattern sums to the dose.
+    I_t = run_forward(spec, d, "obj_true")
+    np.testing.assert_allclose(I_t.sum(axis=(1, 2)), spec.dose, rtol=2e-5)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_loss_grad_parity(torch_cuda, name):
+    spec = CASES[name]
+    say(f"loss/gradient parity: {name}")
+    d = problem(spec)
+    L, lpp, G = run_loss_grad(spec, d)
+    L_ref, lpp_ref, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])
+    eg = rel_l2(G, G_ref)
+    el = abs(L - L_ref) / abs(L_ref)
+    say(f"  loss rel = {el:.3e}, gradient rel L2 = {eg:.3e}")
+    assert el <= TOL_L
+    assert eg <= TOL_G
+    np.testing.assert_allclose(lpp, lpp_ref, rtol=1e-4, atol=1e-6 * np.abs(lpp_ref).max())
+    assert abs(lpp.sum() - L) <= 1e-9 * abs(L)
+    # Locality (Section III): nothing outside the union of windows.
+    cover = np.zeros(G.shape[1:], dtype=bool)
+    for y0, x0 in d["pos"]:
+        cover[y0:y0 + spec.M, x0:x0 + spec.M] = True
+    assert np.all(G[:, ~cover] == 0)
+
+
+def test_zero_gradient_at_truth_noise_free(torch_cuda):
+    spec = ps.with_overrides(ps.workload("ms8-1024-m128"), W=224, ny=4, nx=4, S=4, noise=False)
+    say("zero gradient at the truth (noise-free FP64 measurements)")
+    d = problem(spec)
+    L_t, _, G_t = run_loss_grad(spec, d, "obj_true")
+    L_e, _, G_e = run_loss_grad(spec, d, "obj_eval")
+    # FP32 rounding only: tiny relative to the gradient one step away from the truth.
+    assert np.linalg.norm(G_t) <= 2e-3 * np.linalg.norm(G_e)
+    assert L_t <= 1e-4 * L_e
+
+
+def test_accumulate_and_empty(torch_cuda):
+    import paper_2205_06327_amd as pt
+    import torch
+    spec = ps.reduced(ps.workload("ms8-1024-m128"), W=256, ny=3, nx=3, S=2)
+    say("accumulate flag, empty and single-position calls")
+    d = problem(spec)
+    t = to_dev(d)
+    ctx = context(spec, 16)
+    loss, grad = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"])
+    l1 = float(loss.item())
+    g1 = grad.clone()
+    pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], grad=grad, loss=loss, accumulate=True)
+    torch.cuda.synchronize()
+    assert abs(float(loss.item()) - 2 * l1) <= 1e-12 * abs(l1)
+    assert rel_l2(grad.cpu().numpy(), 2 * g1.cpu().numpy()) <= 1e-6
+    # empty call: zero loss, zeroed gradient
+    e_loss, e_grad = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"][:0], t["meas"][:0], grad=grad)
+    torch.cuda.synchronize()
+    assert float(e_loss.item()) == 0.0 and float(e_grad.abs().max()) == 0.0
+    I0 = pt.ptycho_forward(ctx, t["obj"], t["probe"], t["pos"][:0])
+    assert I0.shape == (0, spec.M, spec.M)
+    # single position equals the oracle
+    L1, _, G1 = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"][:1], d["meas"][:1], d["H"])
+    l_one, g_one = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"][:1].contiguous(), t["meas"][:1].contiguous())
+    ctx.check()
+    assert abs(float(l_one.item()) - L1) <= TOL_L * L1
+    assert rel_l2(g_one.cpu().numpy(), G1) <= TOL_G
+
+
+def test_corner_windows_and_strided_object(torch_cuda):
+    import paper_2205_06327_amd as pt
+    import torch
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=200, S=2, noise=True)
+    say("windows touching every object edge; object given as a strided view")
+    d = problem(spec)
+    W, M = spec.W, spec.M
+    d["pos"] = np.array([[0, 0], [0, W - M], [W - M, 0], [W - M, W - M], [68, 0], [0, 70]], dtype=np.int32)
+    H = d["H"]
+    d["meas"] = ps.poisson_counts(oracle.forward(d["obj_true"], d["probe"], d["pos"], H), d["noise_seed"])
+    t = to_dev(d)
+    big = torch.zeros((spec.S, W + 8, W + 24), dtype=torch.complex64, device="cuda:0")
+    big[:, 3:3 + W, 5:5 + W] = t["obj"]
+    view = big[:, 3:3 + W, 5:5 + W]
+    ctx = context(spec, 16)
+    I = pt.ptycho_forward(ctx, view, t["probe"], t["pos"])
+    loss, G = pt.ptycho_loss_grad(ctx, view, t["probe"], t["pos"], t["meas"])
+    ctx.check()
+    L_ref, _, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], H)
+    assert rel_l2(I.cpu().numpy(), oracle.forward(d["obj_eval"], d["probe"], d["pos"], H)) <= TOL_I
+    assert abs(float(loss.item()) - L_ref) <= TOL_L * L_ref
+    assert rel_l2(G.cpu().numpy(), G_ref) <= TOL_G
+
+
+def test_device_side_window_checks(torch_cuda):
+    import paper_2205_06327_amd as pt
+    import torch
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=128, ny=2, nx=2, step=16)
+    say("device status word: out-of-object window is skipped and reported")
+    d = problem(spec)
+    t = to_dev(d)
+    ctx = context(spec, 16)
+    bad = t["pos"].clone()
+    bad[1, 0] = 100  # 100 + 64 > 128: outside the object
+    I = torch.full((4, 64, 64), -1.0, device="cuda:0")
+    pt.ptycho_forward(ctx, t["obj"], t["probe"], bad, intens=I)
+    with pytest.raises(pt.PtychoError) as e:
+        ctx.check()
+    assert e.value.name == "PTYCHO_E_BOUNDS"
+    assert float(I[1].max()) == -1.0 and float(I[0].min()) >= 0.0
+    assert ctx.check() == 0  # cleared
