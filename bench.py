@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Throughput of the fused forward + amplitude loss + adjoint gradient path.
+
+One step = the whole hot path over one synthetic scan: for every tile of the
+4x4 decomposition, the fused per-position kernel (multislice forward, loss,
+adjoint sweep, scatter-add into the tile's extended box) followed by the
+stitch of the tile gradient into the global gradient.  Inputs are resident in
+HBM when the timed region starts.
+
+Prints one JSON line with probe-positions/s, the roofline of the fused kernel
+(timed with HIP events around each of its launches), the unfused torch-eager
+("plain") path on the same GPU, the FP64 oracle on the host cores, and the
+decomposition checks.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "probe-positions/s, forward+adjoint gradient, fused vs plain; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; packed FP32 is not used by this build.
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP32_PACKED_PEAK_TFLOPS = 157.3
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(M: int, S: int) -> int:
+    """Per position: one pattern read (4 B/px), the S object windows read and the S gradient windows written."""
+    return M * M * (4 + 16 * S)
+
+
+def algorithmic_flops(M: int, S: int) -> float:
+    """Per position: (4S-2) 2D DFTs at 5 N log2 N plus the pointwise work."""
+    N = M * M
+    return (4 * S - 2) * 5.0 * N * math.log2(N) + (30 * S + 10) * N
+
+
+# ---------------------------------------------------------------------------
+# unfused comparator: torch eager ops (rocFFT, elementwise, index_add)
+# ---------------------------------------------------------------------------
+def plain_loss_grad(torch, obj, probe, pos, meas, Hprop, grad, batch):
+    """The same forward/loss/adjoint with one torch op per step, batched over positions."""
+    S, Hh, Ww = obj.shape
+    M = probe.shape[0]
+    ar = torch.arange(M, device=obj.device)
+    total = torch.zeros((), dtype=torch.float64, device=obj.device)
+    flat = [obj[s].reshape(-1) for s in range(S)]
+    gflat = [torch.view_as_real(grad[s]).reshape(-1) for s in range(S)]
+    Hc = Hprop.conj()
+    for b0 in range(0, pos.shape[0], batch):
+        p = pos[b0:b0 + batch].long()
+        lin = ((p[:, 0, None] + ar)[:, :, None] * Ww + (p[:, 1, None] + ar)[:, None, :]).reshape(-1)
+        B = p.shape[0]
+        psi = probe.expand(B, M, M)
+        psis = []
+        phi = None
+        for s in range(S):
+            psis.append(psi)
+            phi = psi * flat[s][lin].view(B, M, M)
+            if s + 1 < S:
+                psi = torch.fft.ifft2(Hprop * torch.fft.fft2(phi))
+        far = torch.fft.fft2(phi)
+        mod = far.abs()
+        amp = meas[b0:b0 + B].sqrt()
+        total += ((mod - amp) ** 2).sum(dtype=torch.float64)
+        scale = torch.where(mod > 0, 2.0 * (mod - amp) / torch.where(mod > 0, mod, torch.ones_like(mod)),
+                            torch.zeros_like(mod))
+        chi = torch.fft.ifft2(scale * far) * float(M * M)
+        idx = torch.stack([2 * lin, 2 * lin + 1], dim=1).reshape(-1)
+        for s in range(S - 1, -1, -1):
+            g = chi * psis[s].conj()
+            gflat[s].index_add_(0, idx, torch.view_as_real(g).reshape(-1))
+            if s > 0:
+                t = flat[s][lin].view(B, M, M)
+                chi = torch.fft.ifft2(Hc * torch.fft.fft2(chi * t.conj()))
+    return total
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle on a sample of positions, over a process pool
+# ---------------------------------------------------------------------------
+_CPU = {}
+
+
+def _cpu_job(i):
+    import oracle
+    d = _CPU
+    return oracle.position_loss_and_patch_gradients(d["obj"][i], d["probe"], 0, 0, d["meas"][i], d["H"])[0]
+
+
+def cpu_baseline(spec, inputs, sample_count, cores):
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import oracle
+    import ptycho_synth as ps
+    from threadpoolctl import threadpool_limits
+
+    pos = inputs["pos"]
+    M, S = spec.M, spec.S
+    idx = np.linspace(0, len(pos) - 1, sample_count).round().astype(int)
+    H = oracle.fresnel_propagator(M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
+    win_eval = np.stack([inputs["obj_eval"][:, y:y + M, x:x + M] for y, x in pos[idx]])
+    win_true = np.stack([inputs["obj_true"][:, y:y + M, x:x + M] for y, x in pos[idx]])
+    with threadpool_limits(1):
+        I = np.stack([oracle.forward(w, inputs["probe"], np.zeros((1, 2), np.int32), H)[0] for w in win_true])
+    meas = ps.poisson_counts(I, np.random.SeedSequence(12345))
+    _CPU.update(obj=win_eval, probe=inputs["probe"], meas=meas, H=H)
+    ctx = mp.get_context("fork")
+    with threadpool_limits(1):
+        with ctx.Pool(cores) as pool:
+            pool.map(_cpu_job, range(min(cores, len(idx))))  # start the workers
+            t0 = time.perf_counter()
+            pool.map(_cpu_job, range(len(idx)), chunksize=max(1, len(idx) // (4 * cores)))
+            dt = time.perf_counter() - t0
+    return {"value": len(idx) / dt, "unit": "positions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{len(idx)} positions spread evenly over the {len(pos)}-position scan, FP64 numpy oracle "
+                      f"(forward + loss + adjoint per position), one process per core, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="ms16-2048-m128-tiles4x4")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-checks", action="store_true", help="skip the undecomposed and streaming comparisons")
+    ap.add_argument("--plain-positions", type=int, default=1024)
+    ap.add_argument("--cpu-sample", type=int, default=768)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        msg = ("this benchmark runs on one GPU only: the decomposed tile walk is measured on a single MI355X; "
+               "multi-GPU tile exchange is not part of this build")
+        print(msg, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2205_06327_amd as pt
+    import ptycho_synth as ps
+    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, StreamingTileWalk, TileWalk
+
+    dev = torch.device("cuda:0")
+    spec = ps.workload(args.workload)
+    M, S, W = spec.M, spec.S, spec.W
+    cores_avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    cores = max(1, min(16, cores_avail))
+    log(f"generating {spec.name}: {S} x {W}^2 object, {spec.n} positions, M={M} ({cores} workers)")
+    t0 = time.time()
+    inputs = ps.build_inputs(spec, workers=cores)
+    log(f"inputs ready in {time.time() - t0:.1f} s")
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is initialised, so the worker processes fork a GPU-free parent
+        log(f"cpu baseline: oracle on {args.cpu_sample} positions over {cores} processes")
+        cpu = cpu_baseline(spec, inputs, args.cpu_sample, cores)
+        log(f"cpu baseline {cpu['value']:.1f} positions/s")
+
+    plan = TileWalk(inputs["pos"], W, W, M, spec.tiles, spec.halo)
+    ctx = pt.Context(M, S, spec.wavelength_A, spec.dz_A, spec.pixel_A, max_positions=spec.n)
+    probe = torch.tensor(inputs["probe"], dtype=torch.complex64, device=dev)
+    pos_sorted = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=dev)
+    obj_true = torch.tensor(inputs["obj_true"], dtype=torch.complex64, device=dev)
+    # measurements: Poisson counts of the noise-free intensities at the truth
+    I_true = pt.ptycho_forward(ctx, obj_true, probe, pos_sorted)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed)
+    meas = torch.poisson(I_true, generator=gen)
+    del I_true, obj_true
+    obj = torch.tensor(inputs["obj_eval"], dtype=torch.complex64, device=dev)
+    grad = torch.empty((S, W, W), dtype=torch.complex64, device=dev)
+    walk = ResidentTileWalk(ctx, plan, device=dev)
+    ctx.check()
+    torch.cuda.synchronize()
+
+    log(f"warmup {args.warmup} steps")
+    for _ in range(args.warmup):
+        walk.step(obj, probe, meas, grad)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    ctx.profile_read()
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss_tiles = walk.step(obj, probe, meas, grad)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    k_ms, k_launches, k_pos = ctx.profile_read()
+    ctx.profile(False)
+    ctx.check()
+    loss_total = float(loss_tiles.sum().item())
+    ms_per_step = dt * 1e3 / args.steps
+    value = spec.n / (ms_per_step / 1e3)
+    log(f"{ms_per_step:.3f} ms/step, {value:.4g} positions/s; fused kernel {k_ms / max(k_launches, 1):.3f} ms/launch")
+
+    Bpos = algorithmic_bytes(M, S)
+    Fpos = algorithmic_flops(M, S)
+    k_s = k_ms / 1e3
+    gbs = k_pos * Bpos / k_s / 1e9
+    tflops = k_pos * Fpos / k_s / 1e12
+    roofline = {
+        "bound": "alu",
+        "achieved": round(tflops, 3),
+        "peak": round(FP32_PEAK_TFLOPS, 2),
+        "unit": "TFLOP/s",
+        "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+        "traffic": None,
+        "kernel": f"fused_kernel<{M},true> (loss+gradient)",
+        "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
+        "launches": k_launches,
+        "positions_per_launch": round(k_pos / max(k_launches, 1), 1),
+        "algorithmic_bytes_per_position": Bpos,
+        "algorithmic_flops_per_position": Fpos,
+        "hbm_achieved_GBs": round(gbs, 1),
+        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+        "frac_vs_packed_fp32_peak": round(tflops / FP32_PACKED_PEAK_TFLOPS, 4),
+    }
+    hbm_roofline_pos = HBM_PEAK_GBS * 1e9 / Bpos
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": spec.name, "positions": spec.n, "slices": S, "object": [W, W], "window": M,
+                   "tiles": list(spec.tiles), "halo": spec.halo, "step_px": spec.step, "dose": spec.dose},
+        "hbm_roofline_positions_per_s": round(hbm_roofline_pos, 1),
+        "hbm_roofline_frac_of_step": round(value / hbm_roofline_pos, 4),
+        "roofline": roofline,
+        "loss": loss_total,
+    }
+
+    if not args.no_checks:
+        log("undecomposed gradient for the decomposition check")
+        gfull = torch.empty_like(grad)
+        loss_full, _ = pt.ptycho_loss_grad(ctx, obj, probe, pos_sorted, meas, grad=gfull)
+        torch.cuda.synchronize()
+        diff = float(torch.linalg.vector_norm(gfull - grad) / torch.linalg.vector_norm(gfull))
+        out["decomposition"] = {
+            "rel_l2_decomposed_vs_undecomposed": diff,
+            "loss_rel_diff": abs(float(loss_full.item()) - loss_total) / abs(loss_total),
+            "undecomposed_gradient_bytes": gfull.numel() * 8,
+            "tile_gradient_bytes": int(walk.tile_buf.numel() * 8),
+        }
+        del gfull
+        # streaming walk: object, measurements and gradient in pinned host memory
+        log("streaming tile walk (host-resident inputs)")
+        obj_h = obj.cpu().pin_memory()
+        meas_h = meas.cpu().pin_memory()
+        grad_h = torch.empty((S, W, W), dtype=torch.complex64).pin_memory()
+        del walk
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        base_alloc = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        sw = StreamingTileWalk(plan, ctx, device=dev)
+        sw.step(obj_h, probe, meas_h, grad_h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw.step(obj_h, probe, meas_h, grad_h)
+        torch.cuda.synchronize()
+        st_ms = (time.perf_counter() - t0) * 1e3
+        peak = torch.cuda.max_memory_allocated() - base_alloc
+        sdiff = float(torch.linalg.vector_norm(grad_h.to(dev) - grad) / torch.linalg.vector_norm(grad))
+        out["streaming"] = {
+            "ms_per_step_including_pcie": round(st_ms, 2),
+            "positions_per_s_including_pcie": round(spec.n / (st_ms / 1e3), 1),
+            "device_bytes_per_tile_walk": sw.device_bytes(),
+            "device_peak_bytes_measured": int(peak),
+            "resident_inputs_bytes": int(obj.numel() * 8 + meas.numel() * 4 + grad.numel() * 8),
+            "rel_l2_vs_resident": sdiff,
+        }
+        del sw, obj_h, meas_h, grad_h
+
+    if not args.no_plain:
+        npl = min(args.plain_positions, spec.n)
+        log(f"plain torch-eager path on {npl} positions")
+        Hprop = torch.tensor(np.fft.fftfreq(M, d=spec.pixel_A), dtype=torch.float64)
+        Hprop = torch.exp(-1j * math.pi * spec.wavelength_A * spec.dz_A * (Hprop[:, None] ** 2 + Hprop[None, :] ** 2))
+        Hprop = Hprop.to(torch.complex64).to(dev)
+        sub_pos = pos_sorted[:npl].contiguous()
+        sub_meas = meas[:npl].contiguous()
+        gplain = torch.zeros_like(grad)
+        plain_loss_grad(torch, obj, probe, sub_pos, sub_meas, Hprop, gplain, 128)  # warm-up
+        gplain.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lp = plain_loss_grad(torch, obj, probe, sub_pos, sub_meas, Hprop, gplain, 128)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t0
+        gf = torch.empty_like(grad)
+        lf, _ = pt.ptycho_loss_grad(ctx, obj, probe, sub_pos, sub_meas, grad=gf)
+        ctx.profile(True)
+        ctx.profile_read()
+        pt.ptycho_loss_grad(ctx, obj, probe, sub_pos, sub_meas, grad=gf)
+        f_ms, _, _ = ctx.profile_read()
+        ctx.profile(False)
+        torch.cuda.synchronize()
+        out["plain"] = {
+            "value": round(npl / tp, 1), "unit": "positions/s", "positions": npl,
+            "what": "torch eager: rocFFT fft2/ifft2, elementwise ops and index_add_, batched 128 positions",
+            "fused_kernel_positions_per_s_same_subset": round(npl / (f_ms / 1e3), 1),
+            "fused_step_over_plain": round(value / (npl / tp), 2),
+            "rel_l2_plain_vs_fused_gradient": float(torch.linalg.vector_norm(gplain - gf) /
+                                                    torch.linalg.vector_norm(gf)),
+            "loss_rel_diff": abs(float(lp.item()) - float(lf.item())) / abs(float(lf.item())),
+        }
+        del gplain, gf
+
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -85,8 +85,10 @@ enum {
  * Angstrom).  The FP32 DFT twiddles and the separable propagator factors are
  * computed in FP64 on the host and rounded once.  `stream` is a hipStream_t
  * (NULL = default stream) on which every later call of this context runs.
- * max_positions bounds n of a single loss/gradient call (the per-position
- * gradient staging lives in the context); 0 picks a default of 4096.
+ * max_positions bounds n of a single loss/gradient call (the context keeps a
+ * per-position loss array of that length); 0 picks a default of 4096.
+ * The context also owns the incident-wave store of the adjoint sweep:
+ * (#CUs) x (S-1) x M*M complex64.
  * Returns PTYCHO_E_UNSUPPORTED for other M or S, PTYCHO_E_NOMEM if the
  * workspace cannot be allocated.
  */
@@ -165,6 +167,37 @@ int ptycho_validate_positions(const int32_t* host_pos, int32_t n, int32_t H, int
 int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int32_t ty, int32_t tx,
                     int32_t halo, int32_t* ty0, int32_t* ty1, int32_t* tx0, int32_t* tx1, int32_t* ey0,
                     int32_t* ey1, int32_t* ex0, int32_t* ex1);
+
+/*
+ * ptycho_tile_accumulate: the stitch step of the decomposition (Section III,
+ * and the final stitch of Alg. 1): adds a tile gradient [S][eh][ew] (dense)
+ * into the global gradient at its extended box (ey0, ex0):
+ *   grad[s*grad_slice_stride + (ey0+y)*grad_ld + ex0 + x] += tile_grad[s][y][x].
+ * Overlapping boxes therefore sum, which is exactly the neighbour-tile gradient
+ * addition of the paper on one device.  The box must lie inside H x W.
+ */
+int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, int32_t ex0, int32_t eh,
+                           int32_t ew, int32_t H, int32_t W, void* grad, int64_t grad_slice_stride,
+                           int32_t grad_ld);
+
+/*
+ * ptycho_zero_gradient: sets S slices of an H x W complex64 array with the
+ * given strides to zero on the context stream (the reset of a gradient or
+ * accumulation buffer; a plain fill kernel, so it may be graph-captured).
+ */
+int ptycho_zero_gradient(ptycho_ctx* ctx, void* grad, int32_t H, int32_t W, int64_t grad_slice_stride,
+                         int32_t grad_ld);
+
+/*
+ * Kernel timing.  While enabled, every launch of the fused forward or
+ * loss/gradient kernel of this context is bracketed by HIP events on the
+ * context stream (a pool of 4096 pairs allocated by the enable call).
+ * ptycho_profile_read synchronises, returns the summed kernel time in ms, the
+ * number of timed launches and the positions they processed, and resets the
+ * counters.
+ */
+int ptycho_profile_enable(ptycho_ctx* ctx, int32_t enable);
+int ptycho_profile_read(ptycho_ctx* ctx, double* total_ms, int64_t* launches, int64_t* positions);
 
 /* Synchronise the context stream; PTYCHO_OK, or the first HIP error, or a
  * negative code for the device status word (which is then cleared). */

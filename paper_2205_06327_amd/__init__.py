@@ -10,7 +10,9 @@ from ._binding import (  # noqa: F401
     lib,
     ptycho_forward,
     ptycho_loss_grad,
+    ptycho_tile_accumulate,
     ptycho_tile_grad,
+    ptycho_zero_gradient,
     tile_box,
     validate_positions,
     version,

@@ -33,6 +33,7 @@ EXPORTED = (
     "ptycho_create", "ptycho_destroy", "ptycho_set_stream", "ptycho_reserve", "ptycho_workspace_bytes",
     "ptycho_forward", "ptycho_loss_grad", "ptycho_tile_grad", "ptycho_bin_positions",
     "ptycho_validate_positions", "ptycho_tile_box", "ptycho_check", "ptycho_last_error", "ptycho_version",
+    "ptycho_tile_accumulate", "ptycho_profile_enable", "ptycho_profile_read", "ptycho_zero_gradient",
 )
 
 
@@ -72,6 +73,12 @@ def lib() -> ctypes.CDLL:
             "ptycho_validate_positions": (ctypes.c_int, [P_i32, c_i32, c_i32, c_i32, c_i32]),
             "ptycho_tile_box": (ctypes.c_int, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32] + [P_i32] * 8),
             "ptycho_check": (ctypes.c_int, [c_vp, ctypes.POINTER(c_u32)]),
+            "ptycho_tile_accumulate": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp,
+                                                      c_i64, c_i32]),
+            "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
+            "ptycho_profile_read": (ctypes.c_int, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
+                                                   ctypes.POINTER(c_i64)]),
             "ptycho_last_error": (ctypes.c_char_p, []),
             "ptycho_version": (ctypes.c_char_p, []),
         }
@@ -196,6 +203,15 @@ class Context:
         _check(lib().ptycho_check(self.handle, ctypes.byref(st)))
         return st.value
 
+    def profile(self, enable: bool = True) -> None:
+        _check(lib().ptycho_profile_enable(self.handle, 1 if enable else 0))
+
+    def profile_read(self):
+        """(kernel ms summed, launches, positions) since the last read."""
+        ms, nl, npos = c_dbl(), c_i64(), c_i64()
+        _check(lib().ptycho_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(npos)))
+        return ms.value, nl.value, npos.value
+
 
 def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
     """I_i = |G(p_i, V)|^2 for every position; returns float32 [n, M, M]."""
@@ -281,3 +297,26 @@ def ptycho_tile_grad(ctx: Context, obj_ext, box, tile, halo: int, H: int, W: int
                                   c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp, c_vp(tile_grad.data_ptr()),
                                   PTYCHO_ACCUMULATE if accumulate else 0))
     return loss, tile_grad
+
+
+def ptycho_tile_accumulate(ctx: Context, tile_grad, box, grad) -> None:
+    """grad[:, ey0:ey0+eh, ex0:ex0+ew] += tile_grad (the stitch of the tile walk)."""
+    torch = _torch()
+    ey0, ex0, eh, ew = box
+    S, H, W = grad.shape
+    _need(tile_grad, torch.complex64, (ctx.S, eh, ew), "tile_grad")
+    if grad.dtype != torch.complex64 or grad.stride(2) != 1 or S != ctx.S:
+        raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
+    ctx._bind_stream()
+    _check(lib().ptycho_tile_accumulate(ctx.handle, c_vp(tile_grad.data_ptr()), ey0, ex0, eh, ew, H, W,
+                                        c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1)))
+
+
+def ptycho_zero_gradient(ctx: Context, grad) -> None:
+    """grad[...] = 0 with the library's fill kernel."""
+    torch = _torch()
+    if grad.dtype != torch.complex64 or grad.dim() != 3 or grad.stride(2) != 1 or grad.shape[0] != ctx.S:
+        raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
+    ctx._bind_stream()
+    _check(lib().ptycho_zero_gradient(ctx.handle, c_vp(grad.data_ptr()), grad.shape[1], grad.shape[2],
+                                      grad.stride(0), grad.stride(1)))

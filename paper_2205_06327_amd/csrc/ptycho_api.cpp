@@ -58,12 +58,19 @@ struct ptycho_ctx {
   double* d_loss = nullptr;  // per-position losses [capacity]
   unsigned* d_status = nullptr;
   int64_t bytes = 0;
+  // kernel timing (ptycho_profile_*)
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;   // pairs: ev[2k] start, ev[2k+1] stop
+  std::vector<int> ev_n;        // positions of launch k
+  size_t ev_used = 0;
+  int64_t dropped = 0;
 };
 
 namespace {
 
 void free_ctx(ptycho_ctx* c) {
   if (!c) return;
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   if (c->d_tw) (void)hipFree(c->d_tw);
   if (c->d_h) (void)hipFree(c->d_h);
   if (c->d_ws) (void)hipFree(c->d_ws);
@@ -107,12 +114,26 @@ ptycho::KernelArgs base_args(const ptycho_ctx* c) {
   return a;
 }
 
+// Launch of a fused kernel, bracketed by timing events when profiling.
+int launch_fused_timed(ptycho_ctx* c, const ptycho::KernelArgs& a, bool grad) {
+  const int grid = a.n < c->grid ? a.n : c->grid;
+  const bool timed = c->profiling && c->ev_used < c->ev_n.size();
+  if (c->profiling && !timed) ++c->dropped;
+  if (timed) PT_HIP(hipEventRecord(c->ev[2 * c->ev_used], c->stream));
+  PT_HIP(ptycho::launch_fused(a, grad, grid, c->stream));
+  if (timed) {
+    PT_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
+    c->ev_n[c->ev_used++] = a.n;
+  }
+  return PTYCHO_OK;
+}
+
 int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, double* loss, uint32_t flags) {
   const bool acc = (flags & PTYCHO_ACCUMULATE) != 0;
   if (!acc) PT_HIP(ptycho::launch_zero_slices(a.grad, c->S, gh, gw, a.gslice, a.gld, c->stream));
   if (a.n > 0) {
-    const int grid = a.n < c->grid ? a.n : c->grid;
-    PT_HIP(ptycho::launch_fused(a, true, grid, c->stream));
+    int rc = launch_fused_timed(c, a, true);
+    if (rc != PTYCHO_OK) return rc;
   }
   PT_HIP(ptycho::launch_finalize_loss(c->d_loss, a.n, loss, acc, c->stream));
   return PTYCHO_OK;
@@ -227,9 +248,7 @@ int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64
   a.probe = static_cast<const float2*>(probe);
   a.pos = pos;
   a.intens = intens;
-  const int grid = n < ctx->grid ? n : ctx->grid;
-  PT_HIP(ptycho::launch_fused(a, false, grid, ctx->stream));
-  return PTYCHO_OK;
+  return launch_fused_timed(ctx, a, false);
 }
 
 int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
@@ -326,6 +345,63 @@ int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t 
   a.gslice = static_cast<long long>(eh) * ew;
   a.gld = ew;
   return run_loss_grad(ctx, a, eh, ew, loss, flags);
+}
+
+int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, int32_t ex0, int32_t eh,
+                           int32_t ew, int32_t H, int32_t W, void* grad, int64_t grad_slice_stride,
+                           int32_t grad_ld) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (!tile_grad || !grad) return fail(PTYCHO_E_ARG, "null gradient pointer");
+  if (eh < 0 || ew < 0 || ey0 < 0 || ex0 < 0 || ey0 + eh > H || ex0 + ew > W)
+    return fail(PTYCHO_E_SHAPE, "box (%d,%d)+(%d,%d) outside %dx%d", ey0, ex0, eh, ew, H, W);
+  if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
+    return fail(PTYCHO_E_SHAPE, "gradient strides do not cover %dx%d", H, W);
+  float2* g = static_cast<float2*>(grad) + static_cast<int64_t>(ey0) * grad_ld + ex0;
+  PT_HIP(ptycho::launch_tile_accumulate(static_cast<const float2*>(tile_grad), ctx->S, eh, ew, g, grad_slice_stride,
+                                        grad_ld, ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_zero_gradient(ptycho_ctx* ctx, void* grad, int32_t H, int32_t W, int64_t grad_slice_stride,
+                         int32_t grad_ld) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (!grad || H < 0 || W < 0) return fail(PTYCHO_E_ARG, "bad gradient buffer");
+  if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
+    return fail(PTYCHO_E_SHAPE, "strides do not cover %dx%d", H, W);
+  PT_HIP(ptycho::launch_zero_slices(static_cast<float2*>(grad), ctx->S, H, W, grad_slice_stride, grad_ld,
+                                    ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_profile_enable(ptycho_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (enable && ctx->ev.empty()) {
+    const size_t pairs = 4096;
+    ctx->ev.resize(2 * pairs, nullptr);
+    for (auto& e : ctx->ev) PT_HIP(hipEventCreate(&e));
+    ctx->ev_n.assign(pairs, 0);
+  }
+  ctx->profiling = enable != 0;
+  return PTYCHO_OK;
+}
+
+int ptycho_profile_read(ptycho_ctx* ctx, double* total_ms, int64_t* launches, int64_t* positions) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  PT_HIP(hipStreamSynchronize(ctx->stream));
+  double tot = 0.0;
+  int64_t np = 0;
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    float ms = 0.f;
+    PT_HIP(hipEventElapsedTime(&ms, ctx->ev[2 * k], ctx->ev[2 * k + 1]));
+    tot += ms;
+    np += ctx->ev_n[k];
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = static_cast<int64_t>(ctx->ev_used);
+  if (positions) *positions = np;
+  ctx->ev_used = 0;
+  ctx->dropped = 0;
+  return PTYCHO_OK;
 }
 
 int ptycho_validate_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t W, int32_t M) {

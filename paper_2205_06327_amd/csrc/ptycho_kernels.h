@@ -33,5 +33,7 @@ hipError_t launch_fused(const KernelArgs& a, bool grad, int grid, hipStream_t st
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);
+hipError_t launch_tile_accumulate(const float2* tile, int S, int eh, int ew, float2* grad, long long gslice,
+                                  long long gld, hipStream_t st);
 
 }  // namespace ptycho

@@ -159,13 +159,18 @@ __device__ __forceinline__ void load_window(float2 (&t)[G::R], const float2* __r
                                             const Lanes<G>& L) {
   for_window_rows<G>(base, ld, L, [&](auto rc, float2 e) { t[decltype(rc)::value] = e; });
 }
-// v *= window (conj_window: v *= conj(window))
+// v *= window (conj_window: v *= conj(window)).  All loads are issued before
+// the first multiply (the scheduling fence keeps the compiler from
+// interleaving them), so the window costs one memory latency, not R.
 template <class G, bool CONJ>
 __device__ __forceinline__ void mul_window(float2 (&v)[G::R], const float2* __restrict__ base, long long ld,
                                            const Lanes<G>& L) {
-  for_window_rows<G>(base, ld, L, [&](auto rc, float2 e) {
+  float2 t[G::R];
+  load_window<G>(t, base, ld, L);
+  __builtin_amdgcn_sched_barrier(0);
+  sfor<G::R>([&](auto rc) {
     constexpr int r = decltype(rc)::value;
-    v[r] = CONJ ? cmulc(v[r], e) : cmul(v[r], e);
+    v[r] = CONJ ? cmulc(v[r], t[r]) : cmul(v[r], t[r]);
   });
 }
 
@@ -279,17 +284,23 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     }
     double acc = 0.0;
     const float* __restrict__ mrow = a.meas + pat;
+    float amp[G::R];
     sfor<G::CJ>([&](auto lc) {
       sfor<G::X2>([&](auto jc) {
         constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
-        float2& e = v[jl * G::X2 + j2];
-        const float amp = sqrtf(mrow[L.jh * G::CJ + jl + G::X1 * j2]);
-        const float mod = sqrtf(e.x * e.x + e.y * e.y);
-        const float d = mod - amp;
-        acc += static_cast<double>(d) * static_cast<double>(d);
-        const float sc = mod > 0.0f ? 2.0f * d / mod : 0.0f;
-        e = make_float2(sc * e.x, sc * e.y);
+        amp[jl * G::X2 + j2] = mrow[L.jh * G::CJ + jl + G::X1 * j2];
       });
+    });
+    __builtin_amdgcn_sched_barrier(0);
+    sfor<G::R>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      float2& e = v[i];
+      const float a_i = sqrtf(amp[i]);
+      const float mod = sqrtf(e.x * e.x + e.y * e.y);
+      const float d = mod - a_i;
+      acc += static_cast<double>(d) * static_cast<double>(d);
+      const float sc = mod > 0.0f ? 2.0f * d / mod : 0.0f;
+      e = make_float2(sc * e.x, sc * e.y);
     });
     // position loss: wave reduction then across the waves through LDS
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
@@ -304,19 +315,30 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
       if (a.loss_pos != nullptr) a.loss_pos[p] = f;
     }
     for (int s = S - 1; s >= 0; --s) {
+      // psi_s and the transmission window are loaded together and consumed
+      // before the gradient atomics are issued: memory operations retire in
+      // order, so loads issued behind the atomics would wait for them.  The
+      // atomics then drain while the next propagation runs on LDS and VALU.
       float2 g[G::R];
       if (s == 0) {
         load_window<G>(g, a.probe, G::M, L);
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
       } else {
+        float2 t[G::R];
         const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
         sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = w[decltype(rc)::value * G::T + L.tid]; });
+        load_window<G>(t, win + s * sstride, ld, L);
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<G::R>([&](auto rc) {
+          constexpr int r = decltype(rc)::value;
+          g[r] = cmulc(v[r], g[r]);
+          v[r] = cmulc(v[r], t[r]);
+        });
       }
-      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
+      __builtin_amdgcn_sched_barrier(0);
       scatter_add<G>(a.grad + s * a.gslice + static_cast<long long>(y0) * a.gld + x0, a.gld, g, L);
-      if (s > 0) {
-        mul_window<G, true>(v, win + s * sstride, ld, L);
-        propagate<G, true>(v, lds, hx_lds, twb, hy, L);
-      }
+      if (s > 0) propagate<G, true>(v, lds, hx_lds, twb, hy, L);
     }
     __syncthreads();  // red[] and lds reuse by the next position
   }
@@ -354,6 +376,21 @@ __global__ void __launch_bounds__(1024) finalize_loss_kernel(const double* __res
 
 __global__ void clear_status_kernel(unsigned* status) { *status = 0u; }
 
+// grad[s, ey0 + y, ex0 + x] += tile[s, y, x]; one thread per complex element.
+__global__ void tile_accumulate_kernel(const float2* __restrict__ tile, int S, int eh, int ew, float2* __restrict__ grad,
+                                       long long gslice, long long gld) {
+  const long long total = static_cast<long long>(S) * eh * ew;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const long long s = i / (static_cast<long long>(eh) * ew);
+    const long long r = i - s * eh * ew;
+    const long long y = r / ew, x = r - y * ew;
+    float2* g = grad + s * gslice + y * gld + x;
+    const float2 t = tile[i];
+    *g = make_float2(g->x + t.x, g->y + t.y);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
@@ -381,6 +418,17 @@ hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, 
 
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st) {
   hipLaunchKernelGGL(finalize_loss_kernel, dim3(1), dim3(1024), 0, st, per, n, loss, accumulate ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_accumulate(const float2* tile, int S, int eh, int ew, float2* grad, long long gslice,
+                                  long long gld, hipStream_t st) {
+  const long long total = static_cast<long long>(S) * eh * ew;
+  if (total == 0) return hipSuccess;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(tile_accumulate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, tile, S, eh, ew,
+                     grad, gslice, gld);
   return hipGetLastError();
 }
 

@@ -3,7 +3,7 @@
 Recipe (the paper's PbTiO3 data are not available, so these stand in for them):
 
 * Object slice: ``phi`` = sum of unit-amplitude Gaussian blobs (sigma 1.5 px,
-  truncated at 6 sigma) centred at lattice sites ``pitch/2 + j*pitch`` jittered
+  truncated at 6 sigma along each axis) centred at lattice sites ``pitch/2 + j*pitch`` jittered
   by U(-0.5, 0.5) px on each axis, min-max normalised to [0, 1]; the slice
   transmission is ``exp(i * strength * phi)`` (a pure-phase object).
 * Probe: integer detector frequencies ``q = fftfreq(M) * M``; aperture
@@ -71,40 +71,63 @@ def atom_phase(W: int, pitch: float, rng: np.random.Generator, sigma: float = 1.
     centres = pitch / 2.0 + pitch * np.arange(nsite)
     cy = centres[:, None] + rng.uniform(-0.5, 0.5, size=(nsite, nsite))
     cx = centres[None, :] + rng.uniform(-0.5, 0.5, size=(nsite, nsite))
-    cy = cy.ravel()
-    cx = cx.ravel()
     iy = np.floor(cy).astype(np.int64)
     ix = np.floor(cx).astype(np.int64)
     fy = cy - iy
     fx = cx - ix
     rad = int(math.ceil(6.0 * sigma))
-    # Accumulate on a canvas padded by the truncation radius, then crop.
-    canvas = np.zeros((W + 2 * rad, W + 2 * rad), dtype=np.float64)
     offs = np.arange(-rad, rad + 1)
-    # Separable Gaussian per atom; for one fixed offset all atoms land on distinct
-    # pixels (sites are >= pitch - 1 > 0 px apart), so a fancy-indexed += is exact.
-    gy = np.exp(-0.5 * ((offs[None, :] - fy[:, None]) / sigma) ** 2)  # [atoms, offs]
-    gx = np.exp(-0.5 * ((offs[None, :] - fx[:, None]) / sigma) ** 2)
-    assert pitch > 1.0
-    keep = (iy >= -rad) & (iy < W + rad) & (ix >= -rad) & (ix < W + rad)
-    iy, ix, gy, gx = iy[keep] + rad, ix[keep] + rad, gy[keep], gx[keep]
-    for a, dy in enumerate(offs):
-        for b, dx in enumerate(offs):
-            if dy * dy + dx * dx > rad * rad:
-                continue
-            canvas[iy + dy, ix + dx] += gy[:, a] * gx[:, b]
+    # Separable Gaussian per atom over a (2 rad + 1)^2 footprint.  The atoms of
+    # one lattice row share a band of canvas rows; their sum over that band is
+    # the product of a (band x atoms) and an (atoms x columns) matrix.
+    Wp = W + 2 * rad
+    canvas = np.zeros((Wp, Wp), dtype=np.float64)
+    cols = np.arange(nsite)[:, None]
+    for i in range(nsite):
+        gy = np.exp(-0.5 * ((offs[None, :] - fy[i][:, None]) / sigma) ** 2)   # [atoms, offs]
+        gx = np.exp(-0.5 * ((offs[None, :] - fx[i][:, None]) / sigma) ** 2)
+        base = int(iy[i].min())
+        Hb = int(iy[i].max()) - base + 2 * rad + 1
+        Gy = np.zeros((nsite, Hb))
+        Gy[cols, (iy[i] - base)[:, None] + offs[None, :] + rad] = gy
+        Gx = np.zeros((nsite, Wp))
+        xi = ix[i][:, None] + offs[None, :] + rad
+        ok = (xi >= 0) & (xi < Wp)
+        Gx[np.broadcast_to(cols, xi.shape)[ok], xi[ok]] = gx[ok]
+        r0 = base - rad + rad  # canvas row of band row 0 (canvas is padded by rad)
+        lo_r, hi_r = max(r0, 0), min(r0 + Hb, Wp)
+        if hi_r > lo_r:
+            canvas[lo_r:hi_r] += (Gy.T @ Gx)[lo_r - r0:hi_r - r0]
     phi = canvas[rad:rad + W, rad:rad + W]
     lo, hi = phi.min(), phi.max()
     return (phi - lo) / (hi - lo) if hi > lo else np.zeros_like(phi)
 
 
-def make_object(W: int, S: int, strength: float, pitch: float, seed_seq: np.random.SeedSequence) -> np.ndarray:
+def _phases(W: int, pitch: float, children, workers: int) -> List[np.ndarray]:
+    if workers > 1 and len(children) > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, len(children))) as ex:
+            return list(ex.map(_phase_job, [(W, pitch, c) for c in children]))
+    return [_phase_job((W, pitch, c)) for c in children]
+
+
+def _phase_job(args) -> np.ndarray:
+    W, pitch, child = args
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        return atom_phase(W, pitch, np.random.default_rng(child))
+    with threadpool_limits(1):
+        return atom_phase(W, pitch, np.random.default_rng(child))
+
+
+def make_object(W: int, S: int, strength: float, pitch: float, seed_seq: np.random.SeedSequence,
+                workers: int = 1) -> np.ndarray:
     """Stack of S independent pure-phase slices exp(i*strength*phi_s), complex128 [S, W, W]."""
-    children = seed_seq.spawn(S)
+    phis = _phases(W, pitch, seed_seq.spawn(S), workers)
     obj = np.empty((S, W, W), dtype=np.complex128)
     for s in range(S):
-        phi = atom_phase(W, pitch, np.random.default_rng(children[s]))
-        obj[s] = np.exp(1j * strength * phi)
+        obj[s] = np.exp(1j * strength * phis[s])
     return obj
 
 
@@ -139,14 +162,14 @@ def poisson_counts(intensity: np.ndarray, seed_seq: np.random.SeedSequence) -> n
     return rng.poisson(lam).astype(np.float32)
 
 
-def eval_object(obj_true: np.ndarray, pitch: float, seed_seq: np.random.SeedSequence, amp: float = 0.01) -> np.ndarray:
+def eval_object(obj_true: np.ndarray, pitch: float, seed_seq: np.random.SeedSequence, amp: float = 0.01,
+                workers: int = 1) -> np.ndarray:
     """A nearby evaluation point t_true * exp(i*amp*phi'), with phi' a fresh lattice draw per slice."""
     S, W, _ = obj_true.shape
-    children = seed_seq.spawn(S)
+    phis = _phases(W, pitch, seed_seq.spawn(S), workers)
     out = np.empty_like(obj_true)
     for s in range(S):
-        phi = atom_phase(W, pitch, np.random.default_rng(children[s]))
-        out[s] = obj_true[s] * np.exp(1j * amp * phi)
+        out[s] = obj_true[s] * np.exp(1j * amp * phis[s])
     return out
 
 
@@ -170,11 +193,11 @@ def workload(name: str) -> WorkloadSpec:
     raise ValueError(f"unknown workload {name!r}; known: {WORKLOAD_NAMES}")
 
 
-def build_inputs(spec: WorkloadSpec, with_eval: bool = True) -> dict:
+def build_inputs(spec: WorkloadSpec, with_eval: bool = True, workers: int = 1) -> dict:
     """Object (truth and a nearby evaluation point), probe and positions for a spec."""
     s_atoms, s_noise, s_fd, _ = seed_streams(spec.seed)
     s_true, s_eval = s_atoms.spawn(2)
-    obj = make_object(spec.W, spec.S, spec.strength, spec.pitch, s_true)
+    obj = make_object(spec.W, spec.S, spec.strength, spec.pitch, s_true, workers)
     out = {
         "spec": spec,
         "obj_true": obj,
@@ -184,7 +207,7 @@ def build_inputs(spec: WorkloadSpec, with_eval: bool = True) -> dict:
         "fd_seed": s_fd,
     }
     if with_eval:
-        out["obj_eval"] = eval_object(obj, spec.pitch, s_eval)
+        out["obj_eval"] = eval_object(obj, spec.pitch, s_eval, workers=workers)
     return out
 
 

@@ -1,0 +1,124 @@
+"""GPU tile decomposition (Section III): per-tile gradients against the oracle,
+the stitched sum against the undecomposed GPU gradient, and the device-side
+halo / assignment checks."""
+import numpy as np
+import pytest
+
+import oracle
+import ptycho_synth as ps
+from gpu_helpers import context, problem, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def tiled_spec():
+    # 4 slices of 384^2, 2x2 tiles with a 64 px halo (= M/2), 18x18 raster with step 14
+    return ps.with_overrides(ps.workload("ms16-2048-m128-tiles4x4"), W=384, S=4, ny=18, nx=18, tiles=(2, 2), halo=64)
+
+
+def test_tile_gradients_match_oracle_and_sum_to_global(torch_cuda):
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, TileWalk
+    spec = tiled_spec()
+    say("tile walk 2x2 on 4 x 384^2, 324 positions")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    walk = ResidentTileWalk(ctx, plan)
+    meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
+    grad = torch.empty_like(t["obj"])
+    losses = walk.step(t["obj"], t["probe"], meas_sorted, grad)
+    ctx.check()
+    gfull = torch.empty_like(grad)
+    lfull, _ = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], grad=gfull)
+    ctx.check()
+    torch.cuda.synchronize()
+    dec = rel_l2(grad.cpu().numpy(), gfull.cpu().numpy())
+    say(f"  decomposed vs undecomposed rel L2 = {dec:.3e}")
+    assert dec <= 1e-6
+    assert abs(float(losses.sum()) - float(lfull.item())) <= 1e-9 * float(lfull.item())
+    G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+    assert rel_l2(grad.cpu().numpy(), G_ref) <= 1e-4
+    # every tile gradient against the oracle's tile gradient
+    for k, p in enumerate(plan.plans):
+        ty, tx = divmod(k, spec.tiles[1])
+        ref = oracle.tile_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"], spec.tiles, spec.halo,
+                                   ty, tx)
+        ey0, ex0, eh, ew = p.box
+        assert ref["box"] == (ey0, ey0 + eh, ex0, ex0 + ew)
+        tg = torch.empty((spec.S, eh, ew), dtype=torch.complex64, device="cuda:0")
+        loss_k, _ = pt.ptycho_tile_grad(ctx, t["obj"][:, ey0:ey0 + eh, ex0:ex0 + ew], p.box, p.tile, spec.halo,
+                                        spec.W, spec.W, t["probe"], walk.pos[p.lo:p.hi], meas_sorted[p.lo:p.hi],
+                                        tile_grad=tg)
+        ctx.check()
+        assert rel_l2(tg.cpu().numpy(), ref["grad"]) <= 1e-4
+        assert abs(float(loss_k.item()) - ref["loss"]) <= 1e-5 * ref["loss"]
+
+
+def test_tile_halo_and_assignment_checks(torch_cuda):
+    import torch
+    import paper_2205_06327_amd as pt
+    spec = tiled_spec()
+    say("device-side halo and assignment checks of the tile gradient")
+    d = problem(spec)
+    t = to_dev(d)
+    ctx = context(spec, spec.n)
+    owner = pt.bin_positions(d["pos"], spec.W, spec.W, spec.M, 2, 2)
+    # tile (1,1) with its own positions but a halo of 32 < M/2: some windows leave the box
+    (ty0, ty1, tx0, tx1), (ey0, ey1, ex0, ex1) = pt.tile_box(spec.W, spec.W, 2, 2, 1, 1, 32)
+    mine = np.nonzero(owner == 3)[0]
+    pos_k = torch.tensor(d["pos"][mine], dtype=torch.int32, device="cuda:0")
+    meas_k = t["meas"][torch.tensor(mine, device="cuda:0")].contiguous()
+    box = (ey0, ex0, ey1 - ey0, ex1 - ex0)
+    pt.ptycho_tile_grad(ctx, t["obj"][:, ey0:ey1, ex0:ex1], box, (ty0, ty1, tx0, tx1), 32, spec.W, spec.W,
+                        t["probe"], pos_k, meas_k)
+    with pytest.raises(pt.PtychoError) as e:
+        ctx.check()
+    assert e.value.name == "PTYCHO_E_HALO"
+    # positions of tile 0 handed to tile 3 with a full halo: centres outside the tile
+    (ty0, ty1, tx0, tx1), (ey0, ey1, ex0, ex1) = pt.tile_box(spec.W, spec.W, 2, 2, 1, 1, 192)
+    other = np.nonzero(owner == 0)[0][-4:]
+    pos_o = torch.tensor(d["pos"][other], dtype=torch.int32, device="cuda:0")
+    meas_o = t["meas"][torch.tensor(other, device="cuda:0")].contiguous()
+    box = (ey0, ex0, ey1 - ey0, ex1 - ex0)
+    pt.ptycho_tile_grad(ctx, t["obj"][:, ey0:ey1, ex0:ex1], box, (ty0, ty1, tx0, tx1), 192, spec.W, spec.W,
+                        t["probe"], pos_o, meas_o)
+    with pytest.raises(pt.PtychoError) as e:
+        ctx.check()
+    assert e.value.name == "PTYCHO_E_ASSIGN"
+    # a box that is not the tile grown by the halo is rejected on the host
+    with pytest.raises(pt.PtychoError) as e:
+        pt.ptycho_tile_grad(ctx, t["obj"][:, 0:200, 0:200], (0, 0, 200, 200), (0, 192, 0, 192), 64, spec.W,
+                            spec.W, t["probe"], pos_o, meas_o)
+    assert e.value.name == "PTYCHO_E_SHAPE"
+
+
+def test_streaming_walk_matches_resident(torch_cuda):
+    import torch
+    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, StreamingTileWalk, TileWalk
+    spec = tiled_spec()
+    say("streaming tile walk (pinned host inputs) vs resident walk")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    order = torch.tensor(plan.order, device="cuda:0")
+    meas_sorted = t["meas"][order].contiguous()
+    grad = torch.empty_like(t["obj"])
+    ResidentTileWalk(ctx, plan).step(t["obj"], t["probe"], meas_sorted, grad)
+    sw = StreamingTileWalk(plan, ctx)
+    gh = torch.empty(tuple(grad.shape), dtype=torch.complex64).pin_memory()
+    sw.step(t["obj"].cpu().pin_memory(), t["probe"], meas_sorted.cpu().pin_memory(), gh)
+    torch.cuda.synchronize()
+    ctx.check()
+    assert rel_l2(gh.numpy(), grad.cpu().numpy()) <= 1e-6
