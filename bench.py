@@ -32,6 +32,27 @@ FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP32_PACKED_PEAK_TFLOPS = 157.3
 
 
+def kernel_source_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("ptycho_kernels.hip", "fft_lds.hpp", "ptycho_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2205_06327_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per fused launch from the committed counter summary, or None when the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", f"fused_kernel_{workload}_hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_source_sha256():
+        return None
+    return rec
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -142,6 +163,8 @@ def main():
     ap.add_argument("--no-checks", action="store_true", help="skip the undecomposed and streaming comparisons")
     ap.add_argument("--plain-positions", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=768)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -153,6 +176,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": src.numel() * 4,
+                          "bytes_written_per_copy": dst.numel() * 4, "copies": 3}))
+        return
 
     import paper_2205_06327_amd as pt
     import ptycho_synth as ps
@@ -224,7 +257,7 @@ def main():
         "unit": "TFLOP/s",
         "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
         "traffic": None,
-        "kernel": f"fused_kernel<{M},true> (loss+gradient)",
+        "kernel": f"fused_kernel<{M}, 2> (loss + gradient)",
         "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
         "launches": k_launches,
         "positions_per_launch": round(k_pos / max(k_launches, 1), 1),
@@ -235,6 +268,12 @@ def main():
         "frac_vs_packed_fp32_peak": round(tflops / FP32_PACKED_PEAK_TFLOPS, 4),
     }
     hbm_roofline_pos = HBM_PEAK_GBS * 1e9 / Bpos
+    tr = measured_traffic(spec.name)
+    if tr is not None:
+        per_launch = tr["traffic_bytes_per_dispatch"]
+        roofline["traffic"] = round(per_launch)
+        roofline["traffic_bytes_per_position"] = round(per_launch / (k_pos / max(k_launches, 1)))
+        roofline["traffic_over_algorithmic"] = round(per_launch / ((k_pos / max(k_launches, 1)) * Bpos), 3)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": args.steps,

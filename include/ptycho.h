@@ -120,13 +120,24 @@ int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64
  *                 same H x W x S extent as obj; set to dF/dRe t + i dF/dIm t
  *                 (or added into it when ACCUMULATE).  It must not alias obj.
  *   meas:         measured intensities float32 [n][M][M] (non-negative).
+ *   grad_scale:   nullable device double; when given, the gradient (not the
+ *                 loss) is multiplied by it (the upstream factor of a chain rule).
  * Where |Psi| = 0 the direction Psi/|Psi| is taken as 0.
  * n must not exceed the context's reserved capacity (PTYCHO_E_CAPACITY).
  */
 int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
                      int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
                      double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride,
-                     int32_t grad_ld, uint32_t flags);
+                     int32_t grad_ld, uint32_t flags, const double* grad_scale);
+
+/*
+ * ptycho_loss: the amplitude cost F (Eq. 1) alone -- the forward sweep and
+ * the detector-plane residual, without the adjoint.  loss / loss_per_pos /
+ * flags as for ptycho_loss_grad.
+ */
+int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                double* loss_per_pos, uint32_t flags);
 
 /*
  * ptycho_tile_grad: the gradient of one tile (Section III): the summed
@@ -198,6 +209,65 @@ int ptycho_zero_gradient(ptycho_ctx* ctx, void* grad, int32_t H, int32_t W, int6
  */
 int ptycho_profile_enable(ptycho_ctx* ctx, int32_t enable);
 int ptycho_profile_read(ptycho_ctx* ctx, double* total_ms, int64_t* launches, int64_t* positions);
+
+/*
+ * Batched reconstructions.  Many independent problems of uneven size (object,
+ * slice count, scan, window size 64 or 128, dose) are served by one persistent
+ * launch per window size that walks a work list of (reconstruction, position)
+ * items; one full-batch gradient-descent iteration t <- t - alpha * dF/dt
+ * (Section II-B, last paragraph of the formulation; the tile update of Alg. 1)
+ * can be recorded once in a hipGraph and replayed.
+ */
+typedef struct ptycho_recon {
+  int32_t M;              /* window side, 64 or 128 */
+  int32_t S;              /* slices, 1..64 */
+  int32_t H, W;           /* object rows and columns (>= M) */
+  int32_t n;              /* positions (>= 0) */
+  int32_t reserved;       /* must be 0 */
+  int64_t slice_stride;   /* object and gradient: element (s,y,x) at [s*slice_stride + y*ld + x] */
+  int64_t ld;             /* >= W; slice_stride >= H*ld when S > 1 */
+  void* obj;              /* device complex64 transmissions, updated in place by the update step */
+  void* grad;             /* device complex64 gradient (same strides), overwritten by each loss/gradient */
+  const void* probe;      /* device complex64 [M][M] */
+  const int32_t* pos;     /* device int32 [n][2] window corners; windows must lie inside H x W */
+  const float* meas;      /* device float32 [n][M][M] measured intensities */
+  double wavelength_A, dz_A, pixel_A;  /* propagator of this reconstruction */
+  double alpha;           /* gradient-descent step */
+} ptycho_recon;
+
+typedef struct ptycho_batch ptycho_batch;
+
+/*
+ * ptycho_batch_create: copies the descriptors (host array of nrecon), builds
+ * the work list and the per-reconstruction propagator tables, and allocates
+ * everything the batch needs (work list, per-item and per-reconstruction
+ * losses, a loss history of history_rows iterations, the incident-wave store
+ * of each window size).  The batch owns a stream of its own (default priority,
+ * non-blocking); callers order their own work against it with
+ * ptycho_batch_sync.  The arrays the descriptors point to stay owned by the
+ * caller and must outlive the batch.
+ */
+int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t nrecon, int32_t history_rows);
+int ptycho_batch_destroy(ptycho_batch* b);
+/* Persistent workgroups of the launch for window size M (the autotuner's knob); 0 restores the default. */
+int ptycho_batch_set_grid(ptycho_batch* b, int32_t M, int32_t grid);
+int ptycho_batch_get_grid(const ptycho_batch* b, int32_t M);
+/* Gradient of every reconstruction (each grad overwritten) and its loss; losses: nullable device double[nrecon]. */
+int ptycho_batch_loss_grad(ptycho_batch* b, double* losses);
+/* t <- t - alpha * grad for every reconstruction; advances the history row. */
+int ptycho_batch_update(ptycho_batch* b);
+/* One iteration: ptycho_batch_loss_grad then ptycho_batch_update. */
+int ptycho_batch_step(ptycho_batch* b);
+/* Record one iteration in a hipGraph (no allocation inside); replay it with ptycho_batch_replay. */
+int ptycho_batch_capture(ptycho_batch* b);
+int ptycho_batch_replay(ptycho_batch* b);
+/* Synchronise the batch stream; reports out-of-object windows (PTYCHO_E_BOUNDS) and HIP errors. */
+int ptycho_batch_sync(ptycho_batch* b);
+/* Copies the loss history (rows x nrecon doubles, row k = loss before the k-th update) to host memory. */
+int ptycho_batch_history(ptycho_batch* b, double* host_out, int32_t* rows_out);
+int ptycho_batch_reset_history(ptycho_batch* b);
+/* The batch stream (a hipStream_t), for callers that enqueue their own work on it. */
+void* ptycho_batch_stream(const ptycho_batch* b);
 
 /* Synchronise the context stream; PTYCHO_OK, or the first HIP error, or a
  * negative code for the device status word (which is then cleared). */

@@ -9,6 +9,7 @@ from ._binding import (  # noqa: F401
     bin_positions,
     lib,
     ptycho_forward,
+    ptycho_loss,
     ptycho_loss_grad,
     ptycho_tile_accumulate,
     ptycho_tile_grad,

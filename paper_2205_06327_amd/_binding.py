@@ -34,6 +34,10 @@ EXPORTED = (
     "ptycho_forward", "ptycho_loss_grad", "ptycho_tile_grad", "ptycho_bin_positions",
     "ptycho_validate_positions", "ptycho_tile_box", "ptycho_check", "ptycho_last_error", "ptycho_version",
     "ptycho_tile_accumulate", "ptycho_profile_enable", "ptycho_profile_read", "ptycho_zero_gradient",
+    "ptycho_loss", "ptycho_batch_create", "ptycho_batch_destroy", "ptycho_batch_set_grid", "ptycho_batch_get_grid",
+    "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
+    "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
+    "ptycho_batch_stream",
 )
 
 
@@ -65,7 +69,9 @@ def lib() -> ctypes.CDLL:
             "ptycho_workspace_bytes": (c_i64, [c_vp]),
             "ptycho_forward": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp]),
             "ptycho_loss_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
-                                                c_vp, c_vp, c_vp, c_i64, c_i32, c_u32]),
+                                                c_vp, c_vp, c_vp, c_i64, c_i32, c_u32, c_vp]),
+            "ptycho_loss": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
+                                           c_vp, c_vp, c_u32]),
             "ptycho_tile_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32,
                                                 c_i32, c_i32, c_i32, c_i32, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp,
                                                 c_vp, c_vp, c_u32]),
@@ -232,9 +238,37 @@ def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
     return intens
 
 
+def ptycho_loss(ctx: Context, obj, probe, pos, meas, loss=None, loss_per_pos=None, accumulate: bool = False):
+    """Amplitude cost F as a float64 [1] device tensor (forward sweep only)."""
+    torch = _torch()
+    S, H, W, ss, ld = _obj_geometry(obj)
+    if S != ctx.S:
+        raise ValueError(f"object has {S} slices, context {ctx.S}")
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(pos, torch.int32, None, "pos")
+    n = pos.shape[0]
+    _need(meas, torch.float32, (n, M, M), "meas")
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=obj.device)
+    _need(loss, torch.float64, (1,), "loss")
+    lpp = c_vp(0)
+    if loss_per_pos is not None:
+        _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
+        lpp = c_vp(loss_per_pos.data_ptr())
+    ctx._bind_stream()
+    _check(lib().ptycho_loss(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                             c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
+                             PTYCHO_ACCUMULATE if accumulate else 0))
+    return loss
+
+
 def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, loss_per_pos=None,
-                     accumulate: bool = False):
-    """(loss float64 [1], grad complex64 [S, H, W]) of the amplitude cost."""
+                     accumulate: bool = False, grad_scale=None):
+    """(loss float64 [1], grad complex64 [S, H, W]) of the amplitude cost.
+
+    grad_scale: optional float64 [1] device tensor multiplying the gradient.
+    """
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
     if S != ctx.S:
@@ -255,11 +289,15 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
     if loss_per_pos is not None:
         _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
         lpp = c_vp(loss_per_pos.data_ptr())
+    gs = c_vp(0)
+    if grad_scale is not None:
+        _need(grad_scale, torch.float64, (1,), "grad_scale")
+        gs = c_vp(grad_scale.data_ptr())
     ctx._bind_stream()
     _check(lib().ptycho_loss_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
                                   c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
                                   c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
-                                  PTYCHO_ACCUMULATE if accumulate else 0))
+                                  PTYCHO_ACCUMULATE if accumulate else 0, gs))
     return loss, grad
 
 

@@ -1,0 +1,43 @@
+"""torch.autograd binding of the amplitude cost with the hand-written adjoint.
+
+``amplitude_loss(ctx, obj, probe, pos, meas)`` returns F(V) (Eq. 1) as a
+float64 scalar tensor.  Its forward runs the loss-only fused kernel and keeps
+nothing but the inputs; its backward calls the fused loss+gradient kernel,
+which runs the multislice forward again for every position, keeps the
+incident waves of that position only for the duration of its own adjoint
+sweep, and scatter-adds dF/dRe t + i dF/dIm t (Eq. 2) scaled by the incoming
+gradient.  Gradients with respect to the probe, positions or measurements are
+not provided.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _binding as B
+
+
+class _AmplitudeLoss(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, obj, probe, pos, meas, lib_ctx):
+        loss = B.ptycho_loss(lib_ctx, obj.detach(), probe.detach(), pos, meas.detach())
+        fctx.save_for_backward(obj, probe, pos, meas)
+        fctx.lib_ctx = lib_ctx
+        return loss.view(())
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        obj, probe, pos, meas = fctx.saved_tensors
+        if fctx.needs_input_grad[1] or fctx.needs_input_grad[3]:
+            raise RuntimeError("amplitude_loss differentiates with respect to the object only")
+        grad = None
+        if fctx.needs_input_grad[0]:
+            scale = grad_out.detach().to(torch.float64).reshape(1).contiguous()
+            _, grad = B.ptycho_loss_grad(fctx.lib_ctx, obj.detach(), probe.detach(), pos, meas.detach(),
+                                         grad_scale=scale)
+        return grad, None, None, None, None
+
+
+def amplitude_loss(lib_ctx: B.Context, obj: torch.Tensor, probe: torch.Tensor, pos: torch.Tensor,
+                   meas: torch.Tensor) -> torch.Tensor:
+    """F(V) = sum_i sum_q (|G(p_i, V)| - sqrt(meas_i))^2 with a fused-kernel adjoint for autograd."""
+    return _AmplitudeLoss.apply(obj, probe, pos, meas, lib_ctx)

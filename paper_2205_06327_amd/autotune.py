@@ -1,0 +1,82 @@
+"""Launch-shape autotuner for batched reconstructions.
+
+For every window-size class of a batch the persistent launch can use a
+different number of workgroups (the register and LDS budget allows one
+128-window workgroup per CU, and up to three 64-window workgroups).  The tuner
+times one full loss/gradient pass of the batch for each candidate with HIP
+events on the batch stream, keeps the fastest, and caches the choice in a JSON
+file keyed by the device and the batch's shape signature, so later runs of the
+same shape skip the search.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+from typing import Dict, Optional
+
+from .batch import Batch
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "ptycho_mi355x", "autotune.json")
+
+
+def signature(batch: Batch, device_name: str) -> str:
+    """Device + per-reconstruction (M, S, H, W, n) list, hashed."""
+    shapes = [(r.probe.shape[0], r.obj.shape[0], r.obj.shape[1], r.obj.shape[2], r.pos.shape[0])
+              for r in batch.recons]
+    h = hashlib.sha1(json.dumps([device_name, shapes]).encode()).hexdigest()[:16]
+    return f"{device_name}:{h}"
+
+
+def _time_pass(batch: Batch, reps: int) -> float:
+    import torch
+    stream = torch.cuda.ExternalStream(batch.stream_ptr)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    batch.loss_grad()  # warm
+    start.record(stream)
+    for _ in range(reps):
+        batch.loss_grad()
+    stop.record(stream)
+    stop.synchronize()
+    return start.elapsed_time(stop) / reps
+
+
+def tune(batch: Batch, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE, use_cache: bool = True) -> Dict:
+    """Pick the workgroup count of each window-size class; returns {M: grid, "ms": best pass time}."""
+    import torch
+    dev = torch.cuda.get_device_properties(0)
+    cus = dev.multi_processor_count
+    key = signature(batch, dev.name)
+    cache = {}
+    if cache_path and use_cache and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        choice = cache[key]
+        for M in (64, 128):
+            batch.set_grid(M, int(choice[str(M)]))
+        return {64: int(choice["64"]), 128: int(choice["128"]), "ms": choice["ms"], "cached": True}
+    ms_in = {64: [cus, 2 * cus, 3 * cus], 128: [cus // 2, cus]}
+    best = {}
+    for M in (64, 128):
+        timings = []
+        for g in ms_in[M]:
+            g = max(1, min(g, 2 * cus * (2 if M == 64 else 1)))
+            batch.set_grid(M, g)
+            timings.append((_time_pass(batch, reps), g))
+        t, g = min(timings)
+        batch.set_grid(M, g)
+        best[M] = g
+    t_best = _time_pass(batch, reps)
+    result = {"64": best[64], "128": best[128], "ms": t_best}
+    if cache_path:
+        cache[key] = result
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return {64: best[64], 128: best[128], "ms": t_best, "cached": False}

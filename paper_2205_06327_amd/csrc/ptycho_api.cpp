@@ -115,12 +115,12 @@ ptycho::KernelArgs base_args(const ptycho_ctx* c) {
 }
 
 // Launch of a fused kernel, bracketed by timing events when profiling.
-int launch_fused_timed(ptycho_ctx* c, const ptycho::KernelArgs& a, bool grad) {
+int launch_fused_timed(ptycho_ctx* c, const ptycho::KernelArgs& a, int mode) {
   const int grid = a.n < c->grid ? a.n : c->grid;
   const bool timed = c->profiling && c->ev_used < c->ev_n.size();
   if (c->profiling && !timed) ++c->dropped;
   if (timed) PT_HIP(hipEventRecord(c->ev[2 * c->ev_used], c->stream));
-  PT_HIP(ptycho::launch_fused(a, grad, grid, c->stream));
+  PT_HIP(ptycho::launch_fused(a, mode, grid, c->stream));
   if (timed) {
     PT_HIP(hipEventRecord(c->ev[2 * c->ev_used + 1], c->stream));
     c->ev_n[c->ev_used++] = a.n;
@@ -132,7 +132,7 @@ int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, d
   const bool acc = (flags & PTYCHO_ACCUMULATE) != 0;
   if (!acc) PT_HIP(ptycho::launch_zero_slices(a.grad, c->S, gh, gw, a.gslice, a.gld, c->stream));
   if (a.n > 0) {
-    int rc = launch_fused_timed(c, a, true);
+    int rc = launch_fused_timed(c, a, ptycho::kModeLossGrad);
     if (rc != PTYCHO_OK) return rc;
   }
   PT_HIP(ptycho::launch_finalize_loss(c->d_loss, a.n, loss, acc, c->stream));
@@ -248,12 +248,13 @@ int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64
   a.probe = static_cast<const float2*>(probe);
   a.pos = pos;
   a.intens = intens;
-  return launch_fused_timed(ctx, a, false);
+  return launch_fused_timed(ctx, a, ptycho::kModeIntensity);
 }
 
 int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
-                     double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld, uint32_t flags) {
+                     double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld, uint32_t flags,
+                     const double* grad_scale) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
   if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
@@ -278,7 +279,37 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
   a.grad = static_cast<float2*>(grad);
   a.gslice = grad_slice_stride;
   a.gld = grad_ld;
+  a.grad_scale = grad_scale;
   return run_loss_grad(ctx, a, H, W, loss, flags);
+}
+
+int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                double* loss_per_pos, uint32_t flags) {
+  int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
+  if (rc != PTYCHO_OK) return rc;
+  if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
+  if (!loss) return fail(PTYCHO_E_ARG, "null loss");
+  if (n > 0 && !meas) return fail(PTYCHO_E_ARG, "null measurements");
+  if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  ptycho::KernelArgs a = base_args(ctx);
+  a.n = n;
+  a.obj = static_cast<const float2*>(obj);
+  a.slice_stride = slice_stride;
+  a.ld = ld;
+  a.bh = H;
+  a.bw = W;
+  a.oob_flag = PTYCHO_STATUS_BOUNDS;
+  a.probe = static_cast<const float2*>(probe);
+  a.pos = pos;
+  a.meas = meas;
+  a.loss_pos = loss_per_pos;
+  if (n > 0) {
+    rc = launch_fused_timed(ctx, a, ptycho::kModeLoss);
+    if (rc != PTYCHO_OK) return rc;
+  }
+  PT_HIP(ptycho::launch_finalize_loss(ctx->d_loss, n, loss, (flags & PTYCHO_ACCUMULATE) != 0, ctx->stream));
+  return PTYCHO_OK;
 }
 
 int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int32_t ty, int32_t tx, int32_t halo,
@@ -437,6 +468,315 @@ int ptycho_bin_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t 
   }
   return PTYCHO_OK;
 }
+
+// ---------------------------------------------------------------------------
+// batched reconstructions
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct ptycho_batch {
+  int nrecon = 0;
+  hipStream_t stream = nullptr;
+  int num_cu = 256;
+  std::vector<ptycho_recon> host;
+  ptycho::BatchRecon* d_recs = nullptr;
+  int* d_items = nullptr;
+  int nitems = 0;
+  double* d_item_loss = nullptr;
+  double* d_losses = nullptr;
+  double* d_hist = nullptr;
+  int hist_rows = 0;
+  int* d_iter = nullptr;
+  float2* d_h = nullptr;     // nrecon * 128 entries
+  float2* d_tw64 = nullptr;
+  float2* d_tw128 = nullptr;
+  unsigned* d_status = nullptr;
+  struct Class {
+    int M = 0, item0 = 0, nitems = 0, smax = 1, grid = 0, grid_default = 0, ws_grid = 0;
+    float2* ws = nullptr;
+  } cls[2];                  // [0] M = 64, [1] M = 128
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void free_batch(ptycho_batch* b) {
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  void* ptrs[] = {b->d_recs, b->d_items, b->d_item_loss, b->d_losses, b->d_hist, b->d_iter, b->d_h,
+                  b->d_tw64, b->d_tw128, b->d_status, b->cls[0].ws, b->cls[1].ws};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+std::vector<float2> twiddles(int M) {
+  std::vector<float2> tw(M);
+  for (int e = 0; e < M; ++e) {
+    const double ang = -2.0 * kPi * e / M;
+    tw[e] = make_float2(static_cast<float>(std::cos(ang)), static_cast<float>(std::sin(ang)));
+  }
+  return tw;
+}
+
+int batch_enqueue_loss_grad(ptycho_batch* b, double* losses) {
+  PT_HIP(ptycho::launch_batch_elementwise(b->d_recs, b->nrecon, 0, nullptr, b->stream));
+  for (auto& c : b->cls) {
+    if (c.nitems == 0) continue;
+    ptycho::BatchArgs a{};
+    a.recs = b->d_recs;
+    a.items = b->d_items;
+    a.item0 = c.item0;
+    a.nitems = c.nitems;
+    a.smax = c.smax;
+    a.tw = c.M == 64 ? b->d_tw64 : b->d_tw128;
+    a.ws = c.ws;
+    a.item_loss = b->d_item_loss;
+    a.status = b->d_status;
+    PT_HIP(ptycho::launch_batch(a, c.M, c.grid, b->stream));
+  }
+  PT_HIP(ptycho::launch_batch_finalize(b->d_recs, b->d_item_loss, losses ? losses : b->d_losses, b->d_hist, b->d_iter,
+                                       b->hist_rows, b->nrecon, b->stream));
+  return PTYCHO_OK;
+}
+
+int batch_enqueue_update(ptycho_batch* b) {
+  PT_HIP(ptycho::launch_batch_elementwise(b->d_recs, b->nrecon, 1, b->d_iter, b->stream));
+  return PTYCHO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t nrecon, int32_t history_rows) {
+  if (!out) return fail(PTYCHO_E_ARG, "null output pointer");
+  *out = nullptr;
+  if (nrecon < 0 || (nrecon > 0 && !recons)) return fail(PTYCHO_E_ARG, "bad reconstruction array");
+  if (history_rows < 0) return fail(PTYCHO_E_ARG, "negative history length");
+  int64_t total_items = 0;
+  for (int r = 0; r < nrecon; ++r) {
+    const ptycho_recon& R = recons[r];
+    if (R.M != 64 && R.M != 128) return fail(PTYCHO_E_UNSUPPORTED, "reconstruction %d: window size %d", r, R.M);
+    if (R.S < 1 || R.S > 64) return fail(PTYCHO_E_UNSUPPORTED, "reconstruction %d: %d slices", r, R.S);
+    if (R.reserved != 0 || R.n < 0) return fail(PTYCHO_E_ARG, "reconstruction %d: bad count", r);
+    if (R.H < R.M || R.W < R.M || R.ld < R.W || (R.S > 1 && R.slice_stride < static_cast<int64_t>(R.H) * R.ld))
+      return fail(PTYCHO_E_SHAPE, "reconstruction %d: object %dx%d with strides (%lld, %lld)", r, R.H, R.W,
+                  static_cast<long long>(R.slice_stride), static_cast<long long>(R.ld));
+    if (R.ld * R.M >= (int64_t(1) << 31)) return fail(PTYCHO_E_SHAPE, "reconstruction %d: row stride too large", r);
+    if (!R.obj || !R.grad || !R.probe || (R.n > 0 && (!R.pos || !R.meas)))
+      return fail(PTYCHO_E_ARG, "reconstruction %d: null pointer", r);
+    if (R.obj == R.grad) return fail(PTYCHO_E_ARG, "reconstruction %d: gradient aliases the object", r);
+    if (!(R.pixel_A > 0) || !std::isfinite(R.wavelength_A) || !std::isfinite(R.dz_A) || !std::isfinite(R.alpha))
+      return fail(PTYCHO_E_ARG, "reconstruction %d: invalid physics or step", r);
+    total_items += R.n;
+  }
+  if (total_items >= (int64_t(1) << 30)) return fail(PTYCHO_E_CAPACITY, "too many positions");
+  ptycho_batch* b = new ptycho_batch();
+  b->nrecon = nrecon;
+  b->host.assign(recons, recons + nrecon);
+  b->hist_rows = history_rows;
+  hipError_t e;
+  int dev = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "batch stream");
+  }
+  // work list grouped by window size, then reconstruction, then position
+  std::vector<ptycho::BatchRecon> recs(nrecon);
+  std::vector<int> items;
+  items.reserve(2 * total_items);
+  std::vector<float2> htab(static_cast<size_t>(nrecon) * 128);
+  for (int ci = 0; ci < 2; ++ci) {
+    auto& c = b->cls[ci];
+    c.M = ci == 0 ? 64 : 128;
+    c.item0 = static_cast<int>(items.size() / 2);
+    for (int r = 0; r < nrecon; ++r) {
+      const ptycho_recon& R = recons[r];
+      if (R.M != c.M) continue;
+      ptycho::BatchRecon& D = recs[r];
+      D.M = R.M;
+      D.S = R.S;
+      D.H = R.H;
+      D.W = R.W;
+      D.n = R.n;
+      D.item0 = static_cast<int>(items.size() / 2);
+      D.slice_stride = R.slice_stride;
+      D.ld = R.ld;
+      D.obj = static_cast<float2*>(R.obj);
+      D.grad = static_cast<float2*>(R.grad);
+      D.probe = static_cast<const float2*>(R.probe);
+      D.pos = R.pos;
+      D.meas = R.meas;
+      D.alpha = static_cast<float>(R.alpha);
+      for (int k = 0; k < R.M; ++k) {
+        const double f = fft_freq(k, R.M, R.pixel_A);
+        const double ph = -kPi * R.wavelength_A * R.dz_A * f * f;
+        htab[static_cast<size_t>(r) * 128 + k] = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
+      }
+      for (int p = 0; p < R.n; ++p) {
+        items.push_back(r);
+        items.push_back(p);
+      }
+      if (R.S > c.smax) c.smax = R.S;
+    }
+    c.nitems = static_cast<int>(items.size() / 2) - c.item0;
+    c.grid_default = b->num_cu * (c.M == 64 ? 2 : 1);
+    c.ws_grid = c.grid_default * 2;  // the autotuner may pick up to twice the default
+    c.grid = c.nitems < c.grid_default ? c.nitems : c.grid_default;
+  }
+  b->nitems = static_cast<int>(items.size() / 2);
+  const auto tw64 = twiddles(64), tw128 = twiddles(128);
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    return bytes == 0 || (e = hipMalloc(p, bytes)) == hipSuccess;
+  };
+  bool ok = alloc(reinterpret_cast<void**>(&b->d_recs), recs.size() * sizeof(ptycho::BatchRecon)) &&
+            alloc(reinterpret_cast<void**>(&b->d_items), items.size() * sizeof(int)) &&
+            alloc(reinterpret_cast<void**>(&b->d_item_loss), static_cast<size_t>(b->nitems) * sizeof(double)) &&
+            alloc(reinterpret_cast<void**>(&b->d_losses), static_cast<size_t>(nrecon) * sizeof(double)) &&
+            alloc(reinterpret_cast<void**>(&b->d_hist), static_cast<size_t>(history_rows) * nrecon * sizeof(double)) &&
+            alloc(reinterpret_cast<void**>(&b->d_iter), sizeof(int)) &&
+            alloc(reinterpret_cast<void**>(&b->d_h), htab.size() * sizeof(float2)) &&
+            alloc(reinterpret_cast<void**>(&b->d_tw64), 64 * sizeof(float2)) &&
+            alloc(reinterpret_cast<void**>(&b->d_tw128), 128 * sizeof(float2)) &&
+            alloc(reinterpret_cast<void**>(&b->d_status), sizeof(unsigned));
+  for (auto& c : b->cls)
+    ok = ok && (c.nitems == 0 || c.smax < 2 ||
+                alloc(reinterpret_cast<void**>(&c.ws),
+                      static_cast<size_t>(c.ws_grid) * (c.smax - 1) * c.M * c.M * sizeof(float2)));
+  if (!ok) {
+    free_batch(b);
+    return fail(PTYCHO_E_NOMEM, "batch allocation failed: %s", hipGetErrorString(e));
+  }
+  for (int r = 0; r < nrecon; ++r) recs[r].h = b->d_h + static_cast<size_t>(r) * 128;
+  if (!history_rows) b->d_hist = nullptr;
+  const int zero = 0;
+  const unsigned uzero = 0;
+  if ((!recs.empty() && (e = hipMemcpy(b->d_recs, recs.data(), recs.size() * sizeof(ptycho::BatchRecon),
+                                       hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!items.empty() &&
+       (e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (!htab.empty() &&
+       (e = hipMemcpy(b->d_h, htab.data(), htab.size() * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess) ||
+      (e = hipMemcpy(b->d_tw64, tw64.data(), 64 * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_tw128, tw128.data(), 128 * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_iter, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_status, &uzero, sizeof uzero, hipMemcpyHostToDevice)) != hipSuccess) {
+    free_batch(b);
+    return hip_fail(e, "batch upload");
+  }
+  *out = b;
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_destroy(ptycho_batch* b) {
+  if (!b) return PTYCHO_OK;
+  (void)hipStreamSynchronize(b->stream);
+  free_batch(b);
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_set_grid(ptycho_batch* b, int32_t M, int32_t grid) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  if (M != 64 && M != 128) return fail(PTYCHO_E_UNSUPPORTED, "window size %d", M);
+  auto& c = b->cls[M == 64 ? 0 : 1];
+  if (grid < 0 || grid > c.ws_grid) return fail(PTYCHO_E_ARG, "grid %d outside [0, %d]", grid, c.ws_grid);
+  if (b->exec) return fail(PTYCHO_E_ARG, "the launch shape is frozen once a graph is captured");
+  const int g = grid == 0 ? c.grid_default : grid;
+  c.grid = c.nitems < g ? c.nitems : g;
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_get_grid(const ptycho_batch* b, int32_t M) {
+  if (!b || (M != 64 && M != 128)) return -1;
+  return b->cls[M == 64 ? 0 : 1].grid;
+}
+
+int ptycho_batch_loss_grad(ptycho_batch* b, double* losses) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  return batch_enqueue_loss_grad(b, losses);
+}
+
+int ptycho_batch_update(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  return batch_enqueue_update(b);
+}
+
+int ptycho_batch_step(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  int rc = batch_enqueue_loss_grad(b, nullptr);
+  return rc != PTYCHO_OK ? rc : batch_enqueue_update(b);
+}
+
+int ptycho_batch_capture(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  if (b->exec) return PTYCHO_OK;
+  PT_HIP(hipStreamSynchronize(b->stream));
+  PT_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = batch_enqueue_loss_grad(b, nullptr);
+  if (rc == PTYCHO_OK) rc = batch_enqueue_update(b);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != PTYCHO_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+  hipGraphExec_t x = nullptr;
+  if ((e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0)) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "hipGraphInstantiate");
+  }
+  b->graph = g;
+  b->exec = x;
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_replay(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  if (!b->exec) return fail(PTYCHO_E_ARG, "no captured graph");
+  PT_HIP(hipGraphLaunch(b->exec, b->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_sync(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  PT_HIP(hipStreamSynchronize(b->stream));
+  unsigned st = 0;
+  PT_HIP(hipMemcpy(&st, b->d_status, sizeof st, hipMemcpyDeviceToHost));
+  if (st) {
+    const unsigned z = 0;
+    PT_HIP(hipMemcpy(b->d_status, &z, sizeof z, hipMemcpyHostToDevice));
+    return fail(PTYCHO_E_BOUNDS, "a window left its object (status 0x%x)", st);
+  }
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_history(ptycho_batch* b, double* host_out, int32_t* rows_out) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  PT_HIP(hipStreamSynchronize(b->stream));
+  int it = 0;
+  PT_HIP(hipMemcpy(&it, b->d_iter, sizeof it, hipMemcpyDeviceToHost));
+  const int rows = it < b->hist_rows ? it : b->hist_rows;
+  if (rows_out) *rows_out = rows;
+  if (host_out && rows > 0)
+    PT_HIP(hipMemcpy(host_out, b->d_hist, static_cast<size_t>(rows) * b->nrecon * sizeof(double),
+                     hipMemcpyDeviceToHost));
+  return PTYCHO_OK;
+}
+
+int ptycho_batch_reset_history(ptycho_batch* b) {
+  if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  PT_HIP(ptycho::launch_set_int(b->d_iter, 0, b->stream));
+  return PTYCHO_OK;
+}
+
+void* ptycho_batch_stream(const ptycho_batch* b) { return b ? static_cast<void*>(b->stream) : nullptr; }
 
 int ptycho_check(ptycho_ctx* ctx, uint32_t* status_out) {
   if (!ctx) return fail(PTYCHO_E_ARG, "null context");

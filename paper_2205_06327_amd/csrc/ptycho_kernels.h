@@ -5,6 +5,11 @@
 
 namespace ptycho {
 
+// what a fused launch produces per position
+constexpr int kModeIntensity = 0;  // |Psi|^2
+constexpr int kModeLoss = 1;       // f_i only
+constexpr int kModeLossGrad = 2;   // f_i and the adjoint gradient
+
 struct KernelArgs {
   int M, S, n;
   // object window source: element (s, y, x) at obj[s*slice_stride + y*ld + x], y, x local to the box
@@ -27,9 +32,40 @@ struct KernelArgs {
   long long gslice, gld;
   float2* ws;            // per-block incident-wave store: grid * (S-1) * M*M
   unsigned* status;
+  const double* grad_scale;  // nullable device scalar multiplying the gradient
 };
 
-hipError_t launch_fused(const KernelArgs& a, bool grad, int grid, hipStream_t st);
+// One reconstruction of a batch (device copy of the public descriptor plus
+// the position of its items in the work list and its propagator table).
+struct BatchRecon {
+  int M, S, H, W, n, item0;
+  long long slice_stride, ld;
+  float2* obj;
+  float2* grad;
+  const float2* probe;
+  const int* pos;
+  const float* meas;
+  const float2* h;
+  float alpha;
+};
+
+struct BatchArgs {
+  const BatchRecon* recs;
+  const int* items;      // (reconstruction, position) pairs, grouped by reconstruction
+  int item0, nitems;     // this launch's slice of the list (one window size)
+  int smax;              // largest slice count in the slice
+  const float2* tw;
+  float2* ws;            // grid * (smax-1) * M*M
+  double* item_loss;     // one per item of the whole list
+  unsigned* status;
+};
+
+hipError_t launch_fused(const KernelArgs& a, int mode, int grid, hipStream_t st);
+hipError_t launch_batch(const BatchArgs& a, int M, int grid, hipStream_t st);
+hipError_t launch_batch_finalize(const BatchRecon* recs, const double* item_loss, double* losses, double* hist,
+                                 const int* iter, int hist_rows, int nrecon, hipStream_t st);
+hipError_t launch_batch_elementwise(const BatchRecon* recs, int nrecon, int mode, int* iter, hipStream_t st);
+hipError_t launch_set_int(int* p, int v, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);

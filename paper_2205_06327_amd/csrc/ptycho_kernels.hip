@@ -222,26 +222,160 @@ __device__ __forceinline__ bool check_window(const KernelArgs& a, int y0, int x0
   return ok;
 }
 
-template <int M, bool GRAD>
+// Everything one position needs, resolved by the caller (uniform across the
+// workgroup).
+struct PositionJob {
+  const float2* win;     // object window origin: element (s, y, x) at win[s*sstride + y*ld + x]
+  long long ld, sstride;
+  int S;
+  const float2* probe;
+  const float* meas;     // this position's pattern [M][M]
+  float* intens;         // this position's output pattern [M][M]
+  float2* grad;          // gradient window origin, element (s, y, x) at grad[s*gslice + y*gld + x]
+  long long gld, gslice;
+  float gscale;          // 2 x the upstream gradient factor
+};
+
+// Per-workgroup state shared by all positions a workgroup processes.
+template <class G>
+struct Shared {
+  float2 lds[G::LDS_ELEMS];
+  float2 hx[G::M];
+  double red[G::T / 64];
+};
+
+// Loads the separable propagator factor of a reconstruction: the x part into
+// LDS, the y part of this thread's layout-C row (with the 1/M^2 of the inverse
+// transform) into registers.  Contains no barrier.
+template <class G>
+__device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* __restrict__ h, const Lanes<G>& L) {
+  load_hx_table<G>(sh.hx, h);
+  const float2 hky = h[L.ky];
+  const float inv_n = 1.0f / float(G::M * G::M);
+  return make_float2(hky.x * inv_n, hky.y * inv_n);
+}
+
+// The whole per-position path (Section II-B and Eq. 1-2): multislice forward,
+// detector plane (intensities, or the amplitude residual and its direction),
+// and for the gradient mode the adjoint sweep with the scatter-add.  Returns
+// the position loss in thread 0 (LOSS modes).  Starts and ends at a point where
+// every LDS read of the previous position has completed.
+template <class G, int MODE>
+__device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
+                                               float2 hy, float2* __restrict__ ws, const Lanes<G>& L) {
+  constexpr bool GRAD = MODE == kModeLossGrad;
+  constexpr bool LOSS = MODE != kModeIntensity;
+  const int S = jb.S;
+  float2 v[G::R];
+  load_window<G>(v, jb.probe, G::M, L);
+  for (int s = 0; s < S; ++s) {
+    if (GRAD && s >= 1) {
+      float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
+      sfor<G::R>([&](auto rc) { w[decltype(rc)::value * G::T + L.tid] = v[decltype(rc)::value]; });
+    }
+    mul_window<G, false>(v, jb.win + s * jb.sstride, jb.ld, L);
+    if (s + 1 < S) propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
+  }
+  dft2_a_to_c<G>(v, sh.lds, twb, L);
+
+  // ---- detector plane, layout C: element (ky, kx = jh*CJ + jl + X1*j2)
+  const long long row = static_cast<long long>(L.ky) * G::M;
+  if (!LOSS) {
+    float* __restrict__ out = jb.intens + row;
+    sfor<G::CJ>([&](auto lc) {
+      sfor<G::X2>([&](auto jc) {
+        constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
+        const float2 e = v[jl * G::X2 + j2];
+        out[L.jh * G::CJ + jl + G::X1 * j2] = e.x * e.x + e.y * e.y;
+      });
+    });
+    return 0.0;
+  }
+  double acc = 0.0;
+  const float* __restrict__ mrow = jb.meas + row;
+  float amp[G::R];
+  sfor<G::CJ>([&](auto lc) {
+    sfor<G::X2>([&](auto jc) {
+      constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
+      amp[jl * G::X2 + j2] = mrow[L.jh * G::CJ + jl + G::X1 * j2];
+    });
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  sfor<G::R>([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    float2& e = v[i];
+    const float a_i = sqrtf(amp[i]);
+    const float mod = sqrtf(e.x * e.x + e.y * e.y);
+    const float d = mod - a_i;
+    acc += static_cast<double>(d) * static_cast<double>(d);
+    const float sc = mod > 0.0f ? jb.gscale * d / mod : 0.0f;
+    e = make_float2(sc * e.x, sc * e.y);
+  });
+  // position loss: wave reduction, then across the waves through LDS
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if ((L.tid & 63) == 0) sh.red[L.tid >> 6] = acc;
+  double f = 0.0;
+  if (!GRAD) {
+    __syncthreads();
+    if (L.tid == 0)
+      for (int w = 0; w < G::T / 64; ++w) f += sh.red[w];
+    return f;  // the next position's first LDS write is preceded by a barrier
+  }
+  // ---- adjoint sweep
+  idft2_c_to_a<G>(v, sh.lds, twb, L);  // chi_{S-1} = DFT^H g (its barriers make red[] visible)
+  if (L.tid == 0)
+    for (int w = 0; w < G::T / 64; ++w) f += sh.red[w];
+  for (int s = S - 1; s >= 0; --s) {
+    // psi_s and the transmission window are loaded together and consumed
+    // before the gradient atomics are issued: memory operations retire in
+    // order, so loads issued behind the atomics would wait for them.  The
+    // atomics then drain while the next propagation runs on LDS and VALU.
+    float2 g[G::R];
+    if (s == 0) {
+      load_window<G>(g, jb.probe, G::M, L);
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
+    } else {
+      float2 t[G::R];
+      const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
+      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = w[decltype(rc)::value * G::T + L.tid]; });
+      load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
+      __builtin_amdgcn_sched_barrier(0);
+      sfor<G::R>([&](auto rc) {
+        constexpr int r = decltype(rc)::value;
+        g[r] = cmulc(v[r], g[r]);
+        v[r] = cmulc(v[r], t[r]);
+      });
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    scatter_add<G>(jb.grad + s * jb.gslice, jb.gld, g, L);
+    if (s > 0) propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
+  }
+  __syncthreads();  // red[] and lds reuse by the next position
+  return f;
+}
+
+template <int M, int MODE>
 __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
   using G = Geo<M>;
-  __shared__ float2 lds[G::LDS_ELEMS];
-  __shared__ float2 hx_lds[G::M];
-  __shared__ double red[G::T / 64];
-
+  constexpr bool LOSS = MODE != kModeIntensity;
+  __shared__ Shared<G> sh;
   const Lanes<G> L;
   float2 twb[G::X1];
   load_twb<G>(twb, a.tw, L.m2);
-  load_hx_table<G>(hx_lds, a.h);
-  const float2 hky = a.h[L.ky];
-  const float inv_n = 1.0f / float(G::M * G::M);
-  const float2 hy = make_float2(hky.x * inv_n, hky.y * inv_n);
+  const float2 hy = load_propagator<G>(sh, a.h, L);
   __syncthreads();
 
   const int S = a.S;
-  const long long ld = a.ld;
-  const long long sstride = a.slice_stride;
   float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * (S > 1 ? S - 1 : 0) * (G::M * G::M);
+  PositionJob jb;
+  jb.ld = a.ld;
+  jb.sstride = a.slice_stride;
+  jb.S = S;
+  jb.probe = a.probe;
+  jb.gld = a.gld;
+  jb.gslice = a.gslice;
+  jb.gscale = 2.0f * (a.grad_scale != nullptr ? static_cast<float>(*a.grad_scale) : 1.0f);
 
   for (int j = 0;; ++j) {
     const int p = job_position(j, a.n, static_cast<int>(gridDim.x));
@@ -249,100 +383,129 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     const int gy = a.pos[2 * p], gx = a.pos[2 * p + 1];
     const int y0 = gy - a.oy, x0 = gx - a.ox;
     if (!check_window(a, y0, x0, gy, gx)) {
-      if (GRAD && threadIdx.x == 0) {
+      if (LOSS && threadIdx.x == 0) {
         a.loss_work[p] = 0.0;
         if (a.loss_pos != nullptr) a.loss_pos[p] = 0.0;
       }
       continue;
     }
-    const float2* __restrict__ win = a.obj + static_cast<long long>(y0) * ld + x0;
-
-    float2 v[G::R];
-    load_window<G>(v, a.probe, G::M, L);
-    for (int s = 0; s < S; ++s) {
-      if (GRAD && s >= 1) {
-        float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
-        sfor<G::R>([&](auto rc) { w[decltype(rc)::value * G::T + L.tid] = v[decltype(rc)::value]; });
-      }
-      mul_window<G, false>(v, win + s * sstride, ld, L);
-      if (s + 1 < S) propagate<G, false>(v, lds, hx_lds, twb, hy, L);
-    }
-    dft2_a_to_c<G>(v, lds, twb, L);
-
-    // ---- detector plane, layout C: element (ky, kx = jh*CJ + jl + X1*j2)
-    const long long pat = static_cast<long long>(p) * (G::M * G::M) + static_cast<long long>(L.ky) * G::M;
-    if (!GRAD) {
-      float* __restrict__ out = a.intens + pat;
-      sfor<G::CJ>([&](auto lc) {
-        sfor<G::X2>([&](auto jc) {
-          constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
-          const float2 e = v[jl * G::X2 + j2];
-          out[L.jh * G::CJ + jl + G::X1 * j2] = e.x * e.x + e.y * e.y;
-        });
-      });
-      continue;
-    }
-    double acc = 0.0;
-    const float* __restrict__ mrow = a.meas + pat;
-    float amp[G::R];
-    sfor<G::CJ>([&](auto lc) {
-      sfor<G::X2>([&](auto jc) {
-        constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
-        amp[jl * G::X2 + j2] = mrow[L.jh * G::CJ + jl + G::X1 * j2];
-      });
-    });
-    __builtin_amdgcn_sched_barrier(0);
-    sfor<G::R>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      float2& e = v[i];
-      const float a_i = sqrtf(amp[i]);
-      const float mod = sqrtf(e.x * e.x + e.y * e.y);
-      const float d = mod - a_i;
-      acc += static_cast<double>(d) * static_cast<double>(d);
-      const float sc = mod > 0.0f ? 2.0f * d / mod : 0.0f;
-      e = make_float2(sc * e.x, sc * e.y);
-    });
-    // position loss: wave reduction then across the waves through LDS
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if ((L.tid & 63) == 0) red[L.tid >> 6] = acc;
-
-    // ---- adjoint sweep
-    idft2_c_to_a<G>(v, lds, twb, L);  // chi_{S-1} = DFT^H g (contains barriers: red[] is visible after it)
-    if (L.tid == 0) {
-      double f = 0.0;
-      for (int w = 0; w < G::T / 64; ++w) f += red[w];
+    jb.win = a.obj + static_cast<long long>(y0) * a.ld + x0;
+    jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
+    jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
+    jb.grad = a.grad + static_cast<long long>(y0) * a.gld + x0;
+    const double f = run_position<G, MODE>(jb, sh, twb, hy, ws, L);
+    if (LOSS && L.tid == 0) {
       a.loss_work[p] = f;
       if (a.loss_pos != nullptr) a.loss_pos[p] = f;
     }
-    for (int s = S - 1; s >= 0; --s) {
-      // psi_s and the transmission window are loaded together and consumed
-      // before the gradient atomics are issued: memory operations retire in
-      // order, so loads issued behind the atomics would wait for them.  The
-      // atomics then drain while the next propagation runs on LDS and VALU.
-      float2 g[G::R];
-      if (s == 0) {
-        load_window<G>(g, a.probe, G::M, L);
-        __builtin_amdgcn_sched_barrier(0);
-        sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
-      } else {
-        float2 t[G::R];
-        const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
-        sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = w[decltype(rc)::value * G::T + L.tid]; });
-        load_window<G>(t, win + s * sstride, ld, L);
-        __builtin_amdgcn_sched_barrier(0);
-        sfor<G::R>([&](auto rc) {
-          constexpr int r = decltype(rc)::value;
-          g[r] = cmulc(v[r], g[r]);
-          v[r] = cmulc(v[r], t[r]);
-        });
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      scatter_add<G>(a.grad + s * a.gslice + static_cast<long long>(y0) * a.gld + x0, a.gld, g, L);
-      if (s > 0) propagate<G, true>(v, lds, hx_lds, twb, hy, L);
-    }
-    __syncthreads();  // red[] and lds reuse by the next position
   }
 }
+
+// ---------------------------------------------------------------------------
+// Batched persistent launch: a work list of (reconstruction, position) items
+// over many independent reconstructions with the same window size (uneven
+// objects, slice counts and scans), one workgroup per CU walking the list.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
+  using G = Geo<M>;
+  __shared__ Shared<G> sh;
+  const Lanes<G> L;
+  float2 twb[G::X1];
+  load_twb<G>(twb, a.tw, L.m2);
+  float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * (a.smax > 1 ? a.smax - 1 : 0) * (G::M * G::M);
+  int cur = -1;
+  float2 hy = make_float2(0.f, 0.f);
+  PositionJob jb;
+  for (int j = 0;; ++j) {
+    const int k = job_position(j, a.nitems, static_cast<int>(gridDim.x));
+    if (k < 0) break;
+    const int item = a.item0 + k;
+    const int r = a.items[2 * item];
+    const int p = a.items[2 * item + 1];
+    const BatchRecon& R = a.recs[r];
+    if (r != cur) {  // uniform: a new reconstruction's propagator
+      __syncthreads();
+      hy = load_propagator<G>(sh, R.h, L);
+      __syncthreads();
+      cur = r;
+    }
+    const int y0 = R.pos[2 * p], x0 = R.pos[2 * p + 1];
+    if (!(y0 >= 0 && x0 >= 0 && y0 + M <= R.H && x0 + M <= R.W)) {
+      if (threadIdx.x == 0) {
+        atomicOr(a.status, 1u);
+        a.item_loss[item] = 0.0;
+      }
+      continue;
+    }
+    jb.win = R.obj + static_cast<long long>(y0) * R.ld + x0;
+    jb.ld = R.ld;
+    jb.sstride = R.slice_stride;
+    jb.S = R.S;
+    jb.probe = R.probe;
+    jb.meas = R.meas + static_cast<long long>(p) * (G::M * G::M);
+    jb.intens = nullptr;
+    jb.grad = R.grad + static_cast<long long>(y0) * R.ld + x0;
+    jb.gld = R.ld;
+    jb.gslice = R.slice_stride;
+    jb.gscale = 2.0f;
+    const double f = run_position<G, kModeLossGrad>(jb, sh, twb, hy, ws, L);
+    if (L.tid == 0) a.item_loss[item] = f;
+  }
+}
+
+// losses[r] = sum of the item losses of reconstruction r in item order; also
+// appends it to the history row *iter (when the history is enabled).
+__global__ void __launch_bounds__(256) batch_finalize_kernel(const BatchRecon* __restrict__ recs,
+                                                             const double* __restrict__ item_loss,
+                                                             double* __restrict__ losses, double* __restrict__ hist,
+                                                             const int* __restrict__ iter, int hist_rows, int nrecon) {
+  __shared__ double part[256];
+  const int r = blockIdx.x;
+  const BatchRecon& R = recs[r];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < R.n; i += blockDim.x) s += item_loss[R.item0 + i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    losses[r] = part[0];
+    if (hist != nullptr) {
+      const int it = *iter;
+      if (it >= 0 && it < hist_rows) hist[static_cast<long long>(it) * nrecon + r] = part[0];
+    }
+  }
+}
+
+// mode 0: grad = 0 for every reconstruction; mode 1: obj -= alpha * grad, and
+// the history row counter advances by one.
+__global__ void batch_elementwise_kernel(const BatchRecon* __restrict__ recs, int mode, int* __restrict__ iter) {
+  const BatchRecon& R = recs[blockIdx.y];
+  const long long total = static_cast<long long>(R.S) * R.H * R.W;
+  const float al = R.alpha;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const long long s = i / (static_cast<long long>(R.H) * R.W);
+    const long long q = i - s * R.H * R.W;
+    const long long y = q / R.W, x = q - y * R.W;
+    const long long o = s * R.slice_stride + y * R.ld + x;
+    if (mode == 0) {
+      R.grad[o] = make_float2(0.f, 0.f);
+    } else {
+      const float2 g = R.grad[o];
+      float2 t = R.obj[o];
+      t.x -= al * g.x;
+      t.y -= al * g.y;
+      R.obj[o] = t;
+    }
+  }
+  if (mode == 1 && iter != nullptr && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *iter += 1;
+}
+
+__global__ void set_int_kernel(int* p, int v) { *p = v; }
 
 // ---------------------------------------------------------------------------
 // small helper kernels
@@ -394,16 +557,56 @@ __global__ void tile_accumulate_kernel(const float2* __restrict__ tile, int S, i
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
-template <int M, bool GRAD>
+template <int M, int MODE>
 static hipError_t launch_fused_t(const KernelArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((fused_kernel<M, GRAD>), dim3(grid), dim3(Geo<M>::T), 0, st, a);
+  hipLaunchKernelGGL((fused_kernel<M, MODE>), dim3(grid), dim3(Geo<M>::T), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_fused(const KernelArgs& a, bool grad, int grid, hipStream_t st) {
-  if (a.M == 128) return grad ? launch_fused_t<128, true>(a, grid, st) : launch_fused_t<128, false>(a, grid, st);
-  if (a.M == 64) return grad ? launch_fused_t<64, true>(a, grid, st) : launch_fused_t<64, false>(a, grid, st);
+template <int M>
+static hipError_t launch_fused_m(const KernelArgs& a, int mode, int grid, hipStream_t st) {
+  switch (mode) {
+    case kModeIntensity: return launch_fused_t<M, kModeIntensity>(a, grid, st);
+    case kModeLoss: return launch_fused_t<M, kModeLoss>(a, grid, st);
+    case kModeLossGrad: return launch_fused_t<M, kModeLossGrad>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fused(const KernelArgs& a, int mode, int grid, hipStream_t st) {
+  if (a.M == 128) return launch_fused_m<128>(a, mode, grid, st);
+  if (a.M == 64) return launch_fused_m<64>(a, mode, grid, st);
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(const BatchArgs& a, int M, int grid, hipStream_t st) {
+  if (M == 128) {
+    hipLaunchKernelGGL((batch_kernel<128>), dim3(grid), dim3(Geo<128>::T), 0, st, a);
+  } else if (M == 64) {
+    hipLaunchKernelGGL((batch_kernel<64>), dim3(grid), dim3(Geo<64>::T), 0, st, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const BatchRecon* recs, const double* item_loss, double* losses, double* hist,
+                                 const int* iter, int hist_rows, int nrecon, hipStream_t st) {
+  if (nrecon == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_finalize_kernel, dim3(nrecon), dim3(256), 0, st, recs, item_loss, losses, hist, iter,
+                     hist_rows, nrecon);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_elementwise(const BatchRecon* recs, int nrecon, int mode, int* iter, hipStream_t st) {
+  if (nrecon == 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_elementwise_kernel, dim3(512, nrecon), dim3(256), 0, st, recs, mode, iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t st) {
+  hipLaunchKernelGGL(set_int_kernel, dim3(1), dim3(1), 0, st, p, v);
+  return hipGetLastError();
 }
 
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st) {

@@ -56,7 +56,8 @@ def test_create_rejects_unsupported_shapes_before_touching_the_device():
 def test_null_context_calls_fail_cleanly():
     lib = pt.lib()
     assert lib.ptycho_forward(None, None, 256, 256, 0, 256, None, None, 0, None) == -1
-    assert lib.ptycho_loss_grad(None, None, 256, 256, 0, 256, None, None, 0, None, None, None, None, 0, 256, 0) == -1
+    assert lib.ptycho_loss_grad(None, None, 256, 256, 0, 256, None, None, 0, None, None, None, None, 0, 256, 0, None) == -1
+    assert lib.ptycho_loss(None, None, 256, 256, 0, 256, None, None, 0, None, None, None, 0) == -1
     assert lib.ptycho_check(None, None) == -1
     assert lib.ptycho_destroy(None) == 0
 
@@ -95,3 +96,29 @@ def test_tile_box_matches_oracle():
                 ey = oracle.tile_bounds(H, ty_n)
                 ex = oracle.tile_bounds(W, tx_n)
                 assert (t0, t1, u0, u1) == (ey[ty], ey[ty + 1], ex[tx], ex[tx + 1])
+
+
+def test_batch_descriptor_layout_and_host_validation():
+    from paper_2205_06327_amd.batch import ReconDesc, _lib
+    assert ctypes.sizeof(ReconDesc) == 112  # 6 int32, 2 int64, 5 pointers, 4 doubles
+    L = _lib()
+    h = ctypes.c_void_p()
+    d = ReconDesc()
+    d.M, d.S, d.H, d.W, d.n = 96, 2, 256, 256, 4
+    d.slice_stride, d.ld = 256 * 256, 256
+    d.obj, d.grad, d.probe, d.pos, d.meas = 16, 32, 48, 64, 80
+    d.wavelength_A, d.dz_A, d.pixel_A, d.alpha = 0.0197, 2.0, 0.1, 1e-3
+    arr = (ReconDesc * 1)(d)
+    assert L.ptycho_batch_create(ctypes.byref(h), arr, 1, 4) == -6
+    arr[0].M = 128
+    arr[0].ld = 100
+    assert L.ptycho_batch_create(ctypes.byref(h), arr, 1, 4) == -2
+    arr[0].ld = 256
+    arr[0].grad = arr[0].obj
+    assert L.ptycho_batch_create(ctypes.byref(h), arr, 1, 4) == -1
+    arr[0].grad = 32
+    arr[0].reserved = 1
+    assert L.ptycho_batch_create(ctypes.byref(h), arr, 1, 4) == -1
+    assert L.ptycho_batch_create(ctypes.byref(h), arr, -1, 4) == -1
+    assert not h.value
+    assert L.ptycho_batch_step(None) == -1 and L.ptycho_batch_destroy(None) == 0

@@ -1,0 +1,138 @@
+"""Batched persistent launch over uneven reconstructions, the gradient-descent
+iteration, its hipGraph replay and the launch-shape autotuner.
+
+Parity: per-reconstruction loss and gradient of the first iteration against
+the FP64 oracle, and the loss trajectory of several iterations against the
+oracle's own gradient descent (relative 1e-4 per iteration)."""
+import numpy as np
+import pytest
+
+import oracle
+import ptycho_synth as ps
+from gpu_helpers import problem, rel_l2, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def small_specs():
+    base = ps.workload("ms8-1024-m128")
+    m64 = ps.workload("2d-256-m64")
+    return [
+        ps.with_overrides(m64, name="b0", W=128, S=1, ny=5, nx=4, step=7, noise=True, seed=101, strength=0.05),
+        ps.with_overrides(base, name="b1", W=192, S=2, ny=3, nx=4, step=14, seed=102),
+        ps.with_overrides(m64, name="b2", W=160, S=3, ny=6, nx=6, step=7, noise=True, seed=103, strength=0.05),
+        ps.with_overrides(base, name="b3", W=256, S=1, ny=5, nx=3, step=14, seed=104, dose=1e4),
+        ps.with_overrides(base, name="b4", W=224, S=4, ny=4, nx=4, step=14, seed=105, dose=1e6),
+        ps.with_overrides(m64, name="b5", W=96, S=2, ny=2, nx=3, step=7, noise=True, seed=106, strength=0.05),
+    ]
+
+
+def build(specs, torch):
+    from paper_2205_06327_amd.batch import Recon, gd_step_size
+    dev = "cuda:0"
+    probs, recons = [], []
+    for sp in specs:
+        d = problem(sp)
+        alpha = gd_step_size(d["probe"], d["pos"], sp.W, sp.W)
+        d["alpha"] = alpha
+        probs.append(d)
+        recons.append(Recon(torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev),
+                            torch.tensor(d["probe"], dtype=torch.complex64, device=dev),
+                            torch.tensor(d["pos"], dtype=torch.int32, device=dev),
+                            torch.tensor(d["meas"], dtype=torch.float32, device=dev),
+                            sp.wavelength_A, sp.dz_A, sp.pixel_A, alpha))
+    return probs, recons
+
+
+def test_batch_first_iteration_matches_oracle(torch_cuda):
+    import torch
+    from paper_2205_06327_amd.batch import Batch
+    specs = small_specs()
+    say("batched loss/gradient: 6 uneven reconstructions (M 64/128, S 1-4)")
+    probs, recons = build(specs, torch)
+    b = Batch(recons, history_rows=4)
+    losses = torch.zeros(len(recons), dtype=torch.float64, device="cuda:0")
+    b.loss_grad(losses)
+    b.sync()
+    for sp, d, r, L in zip(specs, probs, recons, losses.cpu().numpy()):
+        L_ref, _, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])
+        assert abs(L - L_ref) <= 1e-5 * L_ref, sp.name
+        assert rel_l2(r.grad.cpu().numpy(), G_ref) <= 1e-4, sp.name
+
+
+def test_batch_gradient_descent_trajectory_and_graph_replay(torch_cuda):
+    import torch
+    from paper_2205_06327_amd.batch import Batch
+    specs = small_specs()
+    iters = 5
+    say(f"batched gradient descent, {iters} iterations: eager vs oracle, then hipGraph replays vs eager")
+    probs, recons = build(specs, torch)
+    init = [r.obj.clone() for r in recons]
+    b = Batch(recons, history_rows=16)
+    for _ in range(iters):
+        b.step()
+    b.sync()
+    hist = b.history()
+    assert hist.shape == (iters, len(specs))
+    eager_obj = [r.obj.clone() for r in recons]
+    for k, (sp, d) in enumerate(zip(specs, probs)):
+        t = d["obj_eval"].copy()
+        traj = []
+        for _ in range(iters):
+            L, _, G = oracle.loss_and_gradient(t, d["probe"], d["pos"], d["meas"], d["H"])
+            traj.append(L)
+            t = oracle.gd_step(t, G, d["alpha"])
+        traj = np.array(traj)
+        np.testing.assert_allclose(hist[:, k], traj, rtol=1e-4, err_msg=sp.name)
+        assert np.all(np.diff(traj) < 0), sp.name
+        assert np.all(np.diff(hist[:, k]) < 0), sp.name
+    # graph: restore the start, capture one iteration, replay with eager work and syncs in between
+    torch.cuda.synchronize()
+    for r, o in zip(recons, init):
+        r.obj.copy_(o)
+    torch.cuda.synchronize()
+    b.reset_history()
+    b.sync()
+    b.capture()
+    scratch = torch.randn(1 << 20, device="cuda:0")
+    for it in range(iters):
+        b.replay()
+        b.sync()
+        scratch.mul_(1.0001).add_(1.0)  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        h = b.history()
+        assert h.shape[0] == it + 1
+        np.testing.assert_allclose(h[it], hist[it], rtol=1e-6)
+    for r, e in zip(recons, eager_obj):
+        assert rel_l2(r.obj.cpu().numpy(), e.cpu().numpy()) <= 1e-6
+
+
+def test_autotuner_picks_a_valid_shape_and_caches(torch_cuda, tmp_path):
+    import torch
+    from paper_2205_06327_amd.autotune import tune
+    from paper_2205_06327_amd.batch import Batch
+    specs = small_specs()
+    say("autotuner on the small batch")
+    probs, recons = build(specs, torch)
+    b = Batch(recons, history_rows=2)
+    cache = str(tmp_path / "tune.json")
+    first = tune(b, reps=2, cache_path=cache)
+    assert not first["cached"] and first["ms"] > 0
+    losses = torch.zeros(len(recons), dtype=torch.float64, device="cuda:0")
+    b.loss_grad(losses)
+    b.sync()
+    for d, L in zip(probs, losses.cpu().numpy()):
+        L_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[0]
+        assert abs(L - L_ref) <= 1e-5 * L_ref
+    b2 = Batch(recons, history_rows=2)
+    second = tune(b2, reps=2, cache_path=cache)
+    assert second["cached"] and second[64] == first[64] and second[128] == first[128]
+    assert b2.grid(64) == min(first[64], sum(r.pos.shape[0] for r in recons if r.probe.shape[0] == 64))
