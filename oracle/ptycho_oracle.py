@@ -240,17 +240,21 @@ def stitch_tile_gradients(shape: Sequence[int], tile_results: Sequence[Dict[str,
 
 # ---------------------------------------------------------------------------
 # Full-batch gradient descent on the slice transmissions.
-# Reading: the paper gives no step length; alpha = 1 / (2 M^2 max_r sum_i |P(r - r_i)|^2)
-# (the inverse of the largest diagonal of the single-slice Gauss-Newton
-# curvature of the amplitude cost, a conventional safe step).
+# Reading: the paper gives no step length; alpha = 1 / (2 M^2 S max_r sum_i |P(r - r_i)|^2).
+# With unit-modulus slices and a unitary propagator, the far field's
+# sensitivity to all S slices together is at most sqrt(S) times the largest
+# single-slice one (Cauchy-Schwarz over the slices), so the Gauss-Newton
+# curvature of the amplitude cost is bounded by S times the largest
+# single-slice diagonal 2 M^2 max_r sum_i |P(r - r_i)|^2; the step is the
+# inverse of that bound.
 # ---------------------------------------------------------------------------
-def gd_step_size(probe: np.ndarray, pos: np.ndarray, Hobj: int, Wobj: int) -> float:
+def gd_step_size(probe: np.ndarray, pos: np.ndarray, Hobj: int, Wobj: int, S: int) -> float:
     M = probe.shape[0]
     cover = np.zeros((Hobj, Wobj), dtype=np.float64)
     p2 = np.abs(probe) ** 2
     for y0, x0 in np.asarray(pos):
         cover[int(y0):int(y0) + M, int(x0):int(x0) + M] += p2
-    return 1.0 / (2.0 * M * M * float(cover.max()))
+    return 1.0 / (2.0 * M * M * int(S) * float(cover.max()))
 
 
 def gd_step(obj: np.ndarray, grad: np.ndarray, alpha: float) -> np.ndarray:

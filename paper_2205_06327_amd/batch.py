@@ -148,11 +148,15 @@ class Batch:
         return out[: rows.value, : len(self.recons)].copy()
 
 
-def gd_step_size(probe: np.ndarray, pos: np.ndarray, H: int, W: int) -> float:
-    """alpha = 1 / (2 M^2 max_r sum_i |P(r - r_i)|^2), the step used for every reconstruction."""
+def gd_step_size(probe: np.ndarray, pos: np.ndarray, H: int, W: int, S: int) -> float:
+    """alpha = 1 / (2 M^2 S max_r sum_i |P(r - r_i)|^2), the step used for every reconstruction.
+
+    The inverse of a bound on the Gauss-Newton curvature of the amplitude cost
+    over all S unit-modulus slices (S times the largest single-slice diagonal).
+    """
     M = probe.shape[0]
     cover = np.zeros((H, W), dtype=np.float64)
     p2 = np.abs(np.asarray(probe)) ** 2
     for y0, x0 in np.asarray(pos):
         cover[y0:y0 + M, x0:x0 + M] += p2
-    return 1.0 / (2.0 * M * M * float(cover.max()))
+    return 1.0 / (2.0 * M * M * int(S) * float(cover.max()))

@@ -41,7 +41,7 @@ def build(specs, torch):
     probs, recons = [], []
     for sp in specs:
         d = problem(sp)
-        alpha = gd_step_size(d["probe"], d["pos"], sp.W, sp.W)
+        alpha = gd_step_size(d["probe"], d["pos"], sp.W, sp.W, sp.S)
         d["alpha"] = alpha
         probs.append(d)
         recons.append(Recon(torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev),

@@ -308,13 +308,16 @@ def test_decomposed_gradient_sums_to_global():
         oracle.tile_gradient(obj, probe, pos, meas, H, (2, 3), 4, 1, 1)
 
 
-def test_gradient_descent_decreases_loss():
-    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=64, ny=5, nx=5, step=6, S=2, M=32, R=6.0, C=1.0,
+@pytest.mark.parametrize("S", [2, 8])
+def test_gradient_descent_decreases_loss(S):
+    # With eight slices the single-slice step (no factor S) oscillates on this
+    # problem; the bound over all slices descends monotonically.
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=64, ny=5, nx=5, step=6, S=S, M=32, R=6.0, C=1.0,
                              strength=0.5)
     d = ps.build_inputs(spec)
     H = oracle.fresnel_propagator(spec.M, LAM, DZ, PIX)
     meas = oracle.forward(d["obj_true"], d["probe"], d["pos"], H)
-    alpha = oracle.gd_step_size(d["probe"], d["pos"], spec.W, spec.W)
+    alpha = oracle.gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
     t = ps.eval_object(d["obj_true"], spec.pitch, np.random.SeedSequence(99), amp=0.3)
     losses = []
     for _ in range(8):
@@ -323,3 +326,11 @@ def test_gradient_descent_decreases_loss():
         t = oracle.gd_step(t, G, alpha)
     assert all(b < a for a, b in zip(losses, losses[1:]))
     assert losses[-1] < 0.8 * losses[0]
+    if S == 8:  # the step without the slice factor does not descend here
+        t = ps.eval_object(d["obj_true"], spec.pitch, np.random.SeedSequence(99), amp=0.3)
+        big = []
+        for _ in range(8):
+            L, _, G = oracle.loss_and_gradient(t, d["probe"], d["pos"], meas, H)
+            big.append(L)
+            t = oracle.gd_step(t, G, alpha * S)
+        assert not all(b < a for a, b in zip(big, big[1:]))
