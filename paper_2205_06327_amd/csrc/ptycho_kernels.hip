@@ -267,14 +267,20 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   constexpr bool LOSS = MODE != kModeIntensity;
   const int S = jb.S;
   float2 v[G::R];
+  float2 t[G::R];  // the next slice's transmission window, loaded one propagation ahead
   load_window<G>(v, jb.probe, G::M, L);
+  load_window<G>(t, jb.win, jb.ld, L);
   for (int s = 0; s < S; ++s) {
     if (GRAD && s >= 1) {
       float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
       sfor<G::R>([&](auto rc) { w[decltype(rc)::value * G::T + L.tid] = v[decltype(rc)::value]; });
     }
-    mul_window<G, false>(v, jb.win + s * jb.sstride, jb.ld, L);
-    if (s + 1 < S) propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
+    __builtin_amdgcn_sched_barrier(0);
+    sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
+    if (s + 1 < S) {
+      load_window<G>(t, jb.win + (s + 1) * jb.sstride, jb.ld, L);  // in flight during the propagation
+      propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
+    }
   }
   dft2_a_to_c<G>(v, sh.lds, twb, L);
 
@@ -336,7 +342,6 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
     } else {
-      float2 t[G::R];
       const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = w[decltype(rc)::value * G::T + L.tid]; });
       load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);

@@ -9,13 +9,14 @@ neighbour-tile gradient addition and of the final stitch of Alg. 1.
 
 Two ways to run a step:
 
-* ``step_resident``: object, measurements and the global gradient live in HBM;
-  each tile reads its box as a strided view, writes its gradient into one
-  tile-sized buffer that is then added into the global gradient.
-* ``step_streaming``: object and measurements stay in pinned host memory and
-  the global gradient too; per tile only the extended box of the object, the
-  tile's measurements and its gradient are on the device, double-buffered
-  over two streams, so the device footprint is bounded by two tiles.
+* ``ResidentTileWalk.step``: object, measurements and the global gradient
+  live in HBM; each tile reads its box as a strided view, writes its gradient
+  into one tile-sized buffer that is then added into the global gradient.
+* ``StreamingTileWalk.step``: object, measurements and the global gradient
+  stay in pinned host memory; per tile only the extended box of the object,
+  the tile's measurements and positions, its gradient and the global
+  gradient's box are on the device (one set, reused tile after tile on one
+  stream), so the device footprint is bounded by one tile.
 
 All arithmetic runs in libptycho.so; this module only plans and enqueues.
 """
