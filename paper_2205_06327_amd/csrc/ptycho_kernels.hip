@@ -27,6 +27,18 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
+// Streaming (non-temporal) access for the wave store: each stored wave is
+// read back once, so it should not displace the object windows and gradient
+// rows that neighbouring positions reuse from the caches.
+typedef float f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_nt(float2* p, float2 e) {
+  __builtin_nontemporal_store(f2v{e.x, e.y}, reinterpret_cast<f2v*>(p));
+}
+__device__ __forceinline__ float2 load_nt(const float2* p) {
+  const f2v e = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
+  return make_float2(e.x, e.y);
+}
+
 // Position index of the j-th job of this workgroup, or -1 when done.  Blocks
 // are dispatched round-robin over the 8 XCDs; the positions are cut into 8
 // contiguous chunks and chunk x is walked by the blocks of XCD x, so blocks
@@ -194,6 +206,49 @@ __device__ __forceinline__ void scatter_add(float2* __restrict__ gbase, long lon
   });
 }
 
+// Adds a gradient window staged in LDS (row-major, row stride RS1, written by
+// e1_write_a) into the complex gradient rows so that every atomic instruction
+// covers two whole 128-byte lines: a row of M complex values starting at an
+// arbitrary column touches M/16 + 1 lines, and instructions aligned to the
+// lines touch each of them once instead of splitting lines between
+// instructions.  Each wave takes rows wave, wave + T/64, ...; the lines of a
+// row are taken in pairs (lanes 0-31 and 32-63), lanes outside the window are
+// inactive.
+template <class G>
+__device__ __forceinline__ void scatter_add_lines(float2* __restrict__ gbase, long long gld, const float2* lds,
+                                                  const Lanes<G>& L) {
+  constexpr int NW = G::T / 64;
+  constexpr int JMAX = (G::M / 16 + 2) / 2;  // instructions per row when the row is not line-aligned
+  const int lane = L.tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(L.tid >> 6);
+  const int half = lane >> 5;
+  const int e = lane & 31;
+  const float* __restrict__ lf = reinterpret_cast<const float*>(lds + opaque_zero());
+  const int gldz = static_cast<int>(gld) + opaque_zero();
+#pragma unroll 2
+  for (int k = 0; k < G::M / NW; ++k) {
+    const int y = wave + NW * k;
+    float* row = reinterpret_cast<float*>(gbase + static_cast<long long>(y) * gldz);
+    const int delta = static_cast<int>((reinterpret_cast<unsigned long long>(row) >> 3) & 15);
+    const int nline = (delta + G::M + 15) >> 4;
+    float* line0 = row - 2 * delta;  // 128-byte aligned; only in-window floats are touched
+    const float* src = lf + 2 * y * G::RS1;
+    float val[JMAX];
+    bool ok[JMAX];
+    sfor<JMAX>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      const int c = 2 * j + half;
+      const int w2 = 32 * c + e - 2 * delta;
+      ok[j] = c < nline && w2 >= 0 && w2 < 2 * G::M;
+      val[j] = ok[j] ? src[w2] : 0.0f;
+    });
+    sfor<JMAX>([&](auto jc) {
+      constexpr int j = decltype(jc)::value;
+      if (ok[j]) unsafeAtomicAdd(line0 + 32 * (2 * j + half) + e, val[j]);
+    });
+  }
+}
+
 template <class G>
 __device__ __forceinline__ void load_hx_table(float2* hx_lds, const float2* __restrict__ h) {
   for (int i = threadIdx.x; i < G::M; i += G::T) hx_lds[i] = h[i];
@@ -273,7 +328,7 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   for (int s = 0; s < S; ++s) {
     if (GRAD && s >= 1) {
       float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
-      sfor<G::R>([&](auto rc) { w[decltype(rc)::value * G::T + L.tid] = v[decltype(rc)::value]; });
+      sfor<G::R>([&](auto rc) { store_nt(&w[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
     }
     __builtin_amdgcn_sched_barrier(0);
     sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
@@ -343,7 +398,7 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
     } else {
       const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
-      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = w[decltype(rc)::value * G::T + L.tid]; });
+      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
       load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) {
@@ -353,7 +408,10 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       });
     }
     __builtin_amdgcn_sched_barrier(0);
-    scatter_add<G>(jb.grad + s * jb.gslice, jb.gld, g, L);
+    __syncthreads();  // the last transform's LDS reads are done
+    e1_write_a<G>(sh.lds + opaque_zero(), g, L.n2, L.x);
+    __syncthreads();
+    scatter_add_lines<G>(jb.grad + s * jb.gslice, jb.gld, sh.lds, L);
     if (s > 0) propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
   }
   __syncthreads();  // red[] and lds reuse by the next position
