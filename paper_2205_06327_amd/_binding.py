@@ -175,6 +175,7 @@ class Context:
                  max_positions: int = 0):
         self._h = c_vp()
         self.M, self.S = int(M), int(S)
+        self.physics = (float(wavelength_A), float(dz_A), float(pixel_A))
         _check(lib().ptycho_create(ctypes.byref(self._h), self.M, self.S, float(wavelength_A), float(dz_A),
                                    float(pixel_A), int(max_positions), c_vp(_stream_ptr())))
 

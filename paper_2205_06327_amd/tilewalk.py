@@ -11,7 +11,11 @@ Two ways to run a step:
 
 * ``ResidentTileWalk.step``: object, measurements and the global gradient
   live in HBM; each tile reads its box as a strided view, writes its gradient
-  into one tile-sized buffer that is then added into the global gradient.
+  into a tile-sized buffer that is then added into the global gradient.
+  Consecutive tiles alternate between two lanes (a library context, a stream
+  and a tile buffer each), so the next tile's launch fills the CUs that the
+  previous tile's last workgroups leave idle; the stitches still run one after
+  another, in tile order, because neighbouring boxes overlap.
 * ``StreamingTileWalk.step``: object, measurements and the global gradient
   stay in pinned host memory; per tile only the extended box of the object,
   the tile's measurements and positions, its gradient and the global
@@ -67,39 +71,97 @@ class TileWalk:
 
 
 class ResidentTileWalk:
-    """Decomposed gradient of a whole scan with every input resident in HBM."""
+    """Decomposed gradient of a whole scan with every input resident in HBM.
 
-    def __init__(self, ctx: B.Context, plan: TileWalk, device="cuda:0"):
+    ``lanes`` contexts/streams/tile buffers are used round-robin over the
+    tiles (the first context is the caller's; the others are created with the
+    same physics).  Each tile's gradient kernel waits for nothing but the
+    previous use of its own lane; each stitch waits for the previous tile's
+    stitch.
+    """
+
+    def __init__(self, ctx: B.Context, plan: TileWalk, device="cuda:0", lanes: int = 2):
         import torch
         self.ctx, self.plan = ctx, plan
         S = ctx.S
         eh, ew = plan.max_box
-        ctx.reserve(max(plan.max_count, 1))
+        lanes = max(1, int(lanes))
+        self.ctxs = [ctx] + [B.Context(ctx.M, ctx.S, *ctx.physics, max_positions=max(plan.max_count, 1))
+                             for _ in range(lanes - 1)]
+        for c in self.ctxs:
+            c.reserve(max(plan.max_count, 1))
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
         self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
-        self.tile_buf = torch.empty((S, eh, ew), dtype=torch.complex64, device=device)
+        self.tile_bufs = [torch.empty((S, eh, ew), dtype=torch.complex64, device=device) for _ in range(lanes)]
         self.tile_loss = torch.zeros(len(plan.plans), dtype=torch.float64, device=device)
 
+    @property
+    def lanes(self) -> int:
+        return len(self.ctxs)
+
+    def device_bytes(self) -> int:
+        """Tile buffers plus the contexts' workspaces (the walk's own device memory)."""
+        return sum(t.numel() * t.element_size() for t in self.tile_bufs) + sum(c.workspace_bytes()
+                                                                               for c in self.ctxs)
+
     def tile_views(self, k: int):
-        """(tile gradient view, positions, box) of tile k."""
+        """(tile gradient view in tile k's lane buffer, positions, plan) of tile k."""
         p = self.plan.plans[k]
         ey0, ex0, eh, ew = p.box
-        return self.tile_buf.view(-1)[: self.ctx.S * eh * ew].view(self.ctx.S, eh, ew), self.pos[p.lo:p.hi], p
+        buf = self.tile_bufs[k % self.lanes]
+        return buf.view(-1)[: self.ctx.S * eh * ew].view(self.ctx.S, eh, ew), self.pos[p.lo:p.hi], p
+
+    def profile(self, enable: bool = True) -> None:
+        for c in self.ctxs:
+            c.profile(enable)
+
+    def profile_read(self):
+        """(fused-kernel ms summed, launches, positions) over all lanes since the last read."""
+        tot = [0.0, 0, 0]
+        for c in self.ctxs:
+            for i, v in enumerate(c.profile_read()):
+                tot[i] += v
+        return tuple(tot)
+
+    def check(self) -> int:
+        """OR of the status words of all lanes (raises on a HIP error)."""
+        st = 0
+        for c in self.ctxs:
+            st |= c.check()
+        return st
 
     def step(self, obj, probe, meas_sorted, grad):
         """grad <- sum over tiles of the embedded tile gradients; returns the per-tile loss tensor.
 
         obj: complex64 [S, H, W] (device); meas_sorted: float32 [n, M, M] in tile order.
+        Enqueued on the lanes' streams; the caller's current stream waits for all of them.
         """
+        import torch
+        cur = torch.cuda.current_stream()
         B.ptycho_zero_gradient(self.ctx, grad)
+        start = torch.cuda.Event()
+        start.record(cur)
+        for s in self.streams:
+            s.wait_event(start)
+        last_stitch = None
         for k, p in enumerate(self.plan.plans):
             if p.hi == p.lo:
                 continue
+            lane = k % self.lanes
             ey0, ex0, eh, ew = p.box
             tg, pos_k, _ = self.tile_views(k)
-            B.ptycho_tile_grad(self.ctx, obj[:, ey0:ey0 + eh, ex0:ex0 + ew], p.box, p.tile, self.plan.halo,
-                               self.plan.H, self.plan.W, probe, pos_k, meas_sorted[p.lo:p.hi], tile_grad=tg,
-                               loss=self.tile_loss[k:k + 1])
-            B.ptycho_tile_accumulate(self.ctx, tg, p.box, grad)
+            s = self.streams[lane]
+            with torch.cuda.stream(s):
+                B.ptycho_tile_grad(self.ctxs[lane], obj[:, ey0:ey0 + eh, ex0:ex0 + ew], p.box, p.tile,
+                                   self.plan.halo, self.plan.H, self.plan.W, probe, pos_k, meas_sorted[p.lo:p.hi],
+                                   tile_grad=tg, loss=self.tile_loss[k:k + 1])
+                if last_stitch is not None:
+                    s.wait_event(last_stitch)
+                B.ptycho_tile_accumulate(self.ctxs[lane], tg, p.box, grad)
+                last_stitch = torch.cuda.Event()
+                last_stitch.record(s)
+        for s in self.streams:
+            cur.wait_stream(s)
         return self.tile_loss
 
 

@@ -141,7 +141,7 @@ def test_tiled_16_slices_2048_sampled_parity(torch_cuda):
     meas_sorted = meas_d[order].contiguous()
     grad = torch.empty_like(obj)
     tl = walk.step(obj, probe, meas_sorted, grad)
-    ctx.check()
+    walk.check()
     lpp = torch.zeros(len(pos), dtype=torch.float64, device=dev)
     gfull = torch.empty_like(obj)
     lfull, _ = pt.ptycho_loss_grad(ctx, obj, probe, pos_d, meas_d, grad=gfull, loss_per_pos=lpp)

@@ -38,7 +38,8 @@ def test_tile_gradients_match_oracle_and_sum_to_global(torch_cuda):
     meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
     grad = torch.empty_like(t["obj"])
     losses = walk.step(t["obj"], t["probe"], meas_sorted, grad)
-    ctx.check()
+    assert walk.lanes == 2
+    walk.check()
     gfull = torch.empty_like(grad)
     lfull, _ = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], grad=gfull)
     ctx.check()
@@ -122,3 +123,28 @@ def test_streaming_walk_matches_resident(torch_cuda):
     torch.cuda.synchronize()
     ctx.check()
     assert rel_l2(gh.numpy(), grad.cpu().numpy()) <= 1e-6
+
+
+def test_lane_count_does_not_change_the_walk(torch_cuda):
+    import torch
+    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, TileWalk
+    spec = tiled_spec()
+    say("resident walk with 1, 2 and 3 lanes (overlapping tile launches)")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    order = torch.tensor(plan.order, device="cuda:0")
+    meas_sorted = t["meas"][order].contiguous()
+    out = []
+    for lanes in (1, 2, 3):
+        walk = ResidentTileWalk(ctx, plan, lanes=lanes)
+        grad = torch.empty_like(t["obj"])
+        for _ in range(2):  # the second step reuses every lane's buffers
+            loss = walk.step(t["obj"], t["probe"], meas_sorted, grad)
+        assert walk.check() == 0
+        torch.cuda.synchronize()
+        out.append((grad.cpu().numpy(), float(loss.sum())))
+    for g, l in out[1:]:
+        assert rel_l2(g, out[0][0]) <= 1e-6
+        assert abs(l - out[0][1]) <= 1e-9 * abs(out[0][1])
