@@ -315,7 +315,12 @@ __device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* _
 // and for the gradient mode the adjoint sweep with the scatter-add.  Returns
 // the position loss in thread 0 (LOSS modes).  Starts and ends at a point where
 // every LDS read of the previous position has completed.
-template <class G, int MODE>
+// LINES: gradient atomics staged through LDS and aligned to 128-byte lines
+// (scatter_add_lines); otherwise lanes are paired in registers (scatter_add).
+// The staging costs an LDS round trip and two barriers per slice, which pays
+// off for 128-windows over many slices (the tile walk) but not for 64-windows
+// or the short slice stacks of the batched launch.
+template <class G, int MODE, bool LINES = false>
 __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
                                                float2 hy, float2* __restrict__ ws, const Lanes<G>& L) {
   constexpr bool GRAD = MODE == kModeLossGrad;
@@ -408,10 +413,14 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       });
     }
     __builtin_amdgcn_sched_barrier(0);
-    __syncthreads();  // the last transform's LDS reads are done
-    e1_write_a<G>(sh.lds + opaque_zero(), g, L.n2, L.x);
-    __syncthreads();
-    scatter_add_lines<G>(jb.grad + s * jb.gslice, jb.gld, sh.lds, L);
+    if constexpr (LINES) {
+      __syncthreads();  // the last transform's LDS reads are done
+      e1_write_a<G>(sh.lds + opaque_zero(), g, L.n2, L.x);
+      __syncthreads();
+      scatter_add_lines<G>(jb.grad + s * jb.gslice, jb.gld, sh.lds, L);
+    } else {
+      scatter_add<G>(jb.grad + s * jb.gslice, jb.gld, g, L);
+    }
     if (s > 0) propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
   }
   __syncthreads();  // red[] and lds reuse by the next position
@@ -456,7 +465,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
     jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
     jb.grad = a.grad + static_cast<long long>(y0) * a.gld + x0;
-    const double f = run_position<G, MODE>(jb, sh, twb, hy, ws, L);
+    const double f = run_position<G, MODE, G::M == 128>(jb, sh, twb, hy, ws, L);
     if (LOSS && L.tid == 0) {
       a.loss_work[p] = f;
       if (a.loss_pos != nullptr) a.loss_pos[p] = f;
