@@ -40,7 +40,9 @@ orientation), propagator vs the exact angular-spectrum phase, slice-order
 special cases, translation and global-phase covariance, zero gradient at the
 truth, central finite differences, the adjoint dot-product identity, torch
 autograd on tiny grids, the decomposition sum, tile binning by brute force,
-and monotone descent.  ``gd_step_size`` is a reading (the paper states no step
+the directional passes and the neighbour add against the summed tile
+gradients (exact only with tile >= 2 halo for the neighbour add), and
+monotone descent.  ``gd_step_size`` is a reading (the paper states no step
 size): its descent property is tested, its value is not pinned ("parity
 unpinned" for the step length itself).
 """
@@ -63,6 +65,8 @@ __all__ = [
     "tile_gradient",
     "stitch_tile_gradients",
     "gd_step_size",
+    "neighbour_add",
+    "directional_passes",
     "gd_step",
 ]
 
@@ -236,6 +240,83 @@ def stitch_tile_gradients(shape: Sequence[int], tile_results: Sequence[Dict[str,
         ey0, ey1, ex0, ex1 = r["box"]
         out[:, ey0:ey1, ex0:ex1] += r["grad"]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Exchanges between separately held tile buffers (one per device in the
+# paper).  A buffer is {"box": (ey0, ey1, ex0, ex1), "grad": [S, eh, ew]}; the
+# tiles form a tiles_y x tiles_x grid in row-major order.
+# ---------------------------------------------------------------------------
+def _overlap(a: Tuple[int, int, int, int], b: Tuple[int, int, int, int]):
+    """Intersection of two half-open boxes, or None."""
+    y0, y1 = max(a[0], b[0]), min(a[1], b[1])
+    x0, x1 = max(a[2], b[2]), min(a[3], b[3])
+    if y0 >= y1 or x0 >= x1:
+        return None
+    return y0, y1, x0, x1
+
+
+def _view(buf: Dict[str, object], region: Tuple[int, int, int, int]) -> np.ndarray:
+    ey0, _, ex0, _ = buf["box"]
+    y0, y1, x0, x1 = region
+    return buf["grad"][:, y0 - ey0:y1 - ey0, x0 - ex0:x1 - ex0]
+
+
+def neighbour_add(tile_results: Sequence[Dict[str, object]], tiles: Tuple[int, int]) -> List[Dict[str, object]]:
+    """Section IV: every tile adds the gradients of its eight direct neighbours on
+    their overlaps (a single exchange of the original tile gradients)."""
+    ty_n, tx_n = tiles
+    out = [{"box": r["box"], "grad": np.array(r["grad"], copy=True)} for r in tile_results]
+    for ty in range(ty_n):
+        for tx in range(tx_n):
+            k = ty * tx_n + tx
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    if (dy, dx) == (0, 0) or not (0 <= ty + dy < ty_n and 0 <= tx + dx < tx_n):
+                        continue
+                    j = (ty + dy) * tx_n + tx + dx
+                    ov = _overlap(out[k]["box"], tile_results[j]["box"])
+                    if ov is not None:
+                        _view(out[k], ov)[...] += _view(tile_results[j], ov)
+    return out
+
+
+def directional_passes(tile_results: Sequence[Dict[str, object]], tiles: Tuple[int, int]
+                       ) -> List[Dict[str, object]]:
+    """Section V: accumulated-gradient buffers start as copies of the tile
+    gradients; then, in this order,
+      vertical forward   -- down every tile column, the buffer of row r is added
+                            into row r+1 on their overlap;
+      vertical backward  -- up every column, row r+1's buffer replaces row r's
+                            on their overlap;
+      horizontal forward -- along every tile row, column c is added into c+1;
+      horizontal backward -- column c+1 replaces column c on their overlap.
+    Afterwards every buffer holds the summed gradient of all tiles on its box."""
+    ty_n, tx_n = tiles
+    acc = [{"box": r["box"], "grad": np.array(r["grad"], copy=True)} for r in tile_results]
+
+    def exchange(src: int, dst: int, replace: bool) -> None:
+        ov = _overlap(acc[src]["box"], acc[dst]["box"])
+        if ov is None:
+            return
+        if replace:
+            _view(acc[dst], ov)[...] = _view(acc[src], ov)
+        else:
+            _view(acc[dst], ov)[...] += _view(acc[src], ov)
+
+    for tx in range(tx_n):
+        for ty in range(ty_n - 1):
+            exchange(ty * tx_n + tx, (ty + 1) * tx_n + tx, replace=False)
+    for tx in range(tx_n):
+        for ty in range(ty_n - 1, 0, -1):
+            exchange(ty * tx_n + tx, (ty - 1) * tx_n + tx, replace=True)
+    for ty in range(ty_n):
+        for tx in range(tx_n - 1):
+            exchange(ty * tx_n + tx, ty * tx_n + tx + 1, replace=False)
+    for ty in range(ty_n):
+        for tx in range(tx_n - 1, 0, -1):
+            exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
+    return acc
 
 
 # ---------------------------------------------------------------------------

@@ -334,3 +334,55 @@ def test_gradient_descent_decreases_loss(S):
             big.append(L)
             t = oracle.gd_step(t, G, alpha * S)
         assert not all(b < a for a, b in zip(big, big[1:]))
+
+
+def _random_tile_buffers(W, S, tiles, halo, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for ty in range(tiles[0]):
+        for tx in range(tiles[1]):
+            box = oracle.extended_box(W, W, tiles[0], tiles[1], ty, tx, halo)
+            shape = (S, box[1] - box[0], box[3] - box[2])
+            out.append({"box": box, "grad": rng.standard_normal(shape) + 1j * rng.standard_normal(shape)})
+    return out
+
+
+@pytest.mark.parametrize("W,tiles,halo", [
+    (192, (3, 3), 16),   # tile 64 >= 2 * halo: only direct neighbours overlap
+    (192, (4, 4), 32),   # tile 48 < 2 * halo: tiles two apart overlap too
+    (200, (3, 5), 40),   # uneven tiles (66-67 by 40 px), 40 px halo: 2-apart overlaps along x only
+])
+def test_directional_passes_leave_the_global_sum_on_every_box(W, tiles, halo):
+    S = 2
+    bufs = _random_tile_buffers(W, S, tiles, halo, seed=W + halo)
+    total = oracle.stitch_tile_gradients((S, W, W), bufs)
+    acc = oracle.directional_passes(bufs, tiles)
+    for b, a in zip(bufs, acc):
+        ey0, ey1, ex0, ex1 = b["box"]
+        np.testing.assert_allclose(a["grad"], total[:, ey0:ey1, ex0:ex1], rtol=0, atol=1e-12 * np.abs(total).max())
+    # the single direct-neighbour exchange of Section IV is exact only when no two
+    # non-adjacent tiles overlap (tile >= 2 * halo on both axes)
+    nb = oracle.neighbour_add(bufs, tiles)
+    exact = all(np.allclose(n["grad"], total[:, n["box"][0]:n["box"][1], n["box"][2]:n["box"][3]], rtol=0,
+                            atol=1e-12 * np.abs(total).max()) for n in nb)
+    t_min = min(W // tiles[0], W // tiles[1])
+    assert exact == (t_min >= 2 * halo)
+
+
+def test_directional_passes_on_physical_tile_gradients():
+    # 16-windows, 4 x 4 tiles of 12-13 px with an 8 px halo (= M/2), so tiles two apart overlap;
+    # every tile's buffer must end with the undecomposed gradient on its box
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=50, ny=5, nx=5, step=7, S=2, M=16, R=4.0, C=1.0,
+                             strength=0.3)
+    d = ps.build_inputs(spec, with_eval=True)
+    H = oracle.fresnel_propagator(spec.M, LAM, DZ, PIX)
+    meas = oracle.forward(d["obj_true"], d["probe"], d["pos"], H)
+    tiles, halo = (4, 4), 8
+    parts = [oracle.tile_gradient(d["obj_eval"], d["probe"], d["pos"], meas, H, tiles, halo, ty, tx)
+             for ty in range(4) for tx in range(4)]
+    assert sum(len(p["positions"]) for p in parts) == len(d["pos"])
+    G = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], meas, H)[2]
+    acc = oracle.directional_passes(parts, tiles)
+    for a in acc:
+        ey0, ey1, ex0, ex1 = a["box"]
+        np.testing.assert_allclose(a["grad"], G[:, ey0:ey1, ex0:ex1], rtol=0, atol=1e-12 * np.abs(G).max())
