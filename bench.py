@@ -275,7 +275,7 @@ def main():
 
     import paper_2205_06327_amd as pt
     import ptycho_synth as ps
-    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, StreamingTileWalk, TileWalk
+    from paper_2205_06327_amd.tilewalk import DecomposedTileWalk, ResidentTileWalk, StreamingTileWalk, TileWalk
 
     dev = torch.device("cuda:0")
     cores_avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -392,7 +392,37 @@ def main():
             "tile_gradient_bytes": int(walk.tile_bufs[0].numel() * 8),
             "tile_walk_lanes": walk.lanes,
         }
-        del gfull
+        # per-tile accumulated-gradient buffers and the directional passes between them
+        log("per-tile buffers and directional passes")
+        dwalk = DecomposedTileWalk(ctx, plan, device=dev, lanes=args.lanes)
+        dwalk.step(obj, probe, meas)
+        dwalk.check()
+        worst = 0.0
+        for k, p in enumerate(plan.plans):
+            ey0, ex0, eh, ew = p.box
+            ref = gfull[:, ey0:ey0 + eh, ex0:ex0 + ew]
+            worst = max(worst, float(torch.linalg.vector_norm(dwalk.bufs[k] - ref) / torch.linalg.vector_norm(ref)))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            dwalk.passes()
+        e1.record()
+        e1.synchronize()
+        pass_ms = e0.elapsed_time(e1) / reps
+        ty_n, tx_n = plan.tiles
+        out["passes"] = {
+            "what": "vertical forward add, vertical backward replace, horizontal forward add, horizontal backward "
+                    "replace between separately held tile buffers",
+            "exchanges": 2 * (ty_n - 1) * tx_n + 2 * ty_n * (tx_n - 1),
+            "ms": round(pass_ms, 4),
+            "bytes": dwalk.pass_bytes(),
+            "GBs": round(dwalk.pass_bytes() / (pass_ms / 1e3) / 1e9, 1),
+            "max_rel_l2_tile_buffer_vs_undecomposed": worst,
+            "all_tile_buffers_bytes": dwalk.device_bytes(),
+        }
+        del dwalk, gfull
         # streaming walk: object, measurements and gradient in pinned host memory
         log("streaming tile walk (host-resident inputs)")
         obj_h = obj.cpu().pin_memory()

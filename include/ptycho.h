@@ -192,6 +192,27 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
                            int32_t grad_ld);
 
 /*
+ * ptycho_box_exchange: one exchange of the accumulation passes between two
+ * tiles' separately held gradient buffers (Section V; the buffers stand for
+ * the accumulated-gradient buffers that neighbouring devices exchange).  On
+ * the overlap of the two boxes, in global pixel coordinates,
+ *   PTYCHO_EXCHANGE_ADD:     dst += src   (the forward passes, and the
+ *                                          neighbour add of Section IV)
+ *   PTYCHO_EXCHANGE_REPLACE: dst  = src   (the backward passes).
+ * src holds the box with top-left (sy0, sx0) and size sh x sw:
+ * element (s, y, x) of the box at src[s*s_slice_stride + y*s_ld + x]; dst
+ * likewise.  Both are device complex64 arrays owned by the caller; they must
+ * not share memory (E_ARG if the address ranges intersect).  S slices.
+ * Boxes that do not overlap enqueue nothing.  Stream-ordered on the context
+ * stream; allocates nothing.
+ */
+#define PTYCHO_EXCHANGE_ADD 0u
+#define PTYCHO_EXCHANGE_REPLACE 1u
+int ptycho_box_exchange(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
+                        int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0,
+                        int32_t dh, int32_t dw, int64_t d_slice_stride, int32_t d_ld, uint32_t mode);
+
+/*
  * ptycho_zero_gradient: sets S slices of an H x W complex64 array with the
  * given strides to zero on the context stream (the reset of a gradient or
  * accumulation buffer; a plain fill kernel, so it may be graph-captured).

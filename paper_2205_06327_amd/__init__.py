@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     ptycho_tile_accumulate,
     ptycho_tile_grad,
     ptycho_zero_gradient,
+    ptycho_box_exchange,
     tile_box,
     validate_positions,
     version,

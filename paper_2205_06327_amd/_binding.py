@@ -37,7 +37,7 @@ EXPORTED = (
     "ptycho_loss", "ptycho_batch_create", "ptycho_batch_destroy", "ptycho_batch_set_grid", "ptycho_batch_get_grid",
     "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
-    "ptycho_batch_stream",
+    "ptycho_batch_stream", "ptycho_box_exchange",
 )
 
 
@@ -83,6 +83,8 @@ def lib() -> ctypes.CDLL:
                                                       c_i64, c_i32]),
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
+            "ptycho_box_exchange": (ctypes.c_int, [c_vp, c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32,
+                                                   c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_u32]),
             "ptycho_profile_read": (ctypes.c_int, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
                                                    ctypes.POINTER(c_i64)]),
             "ptycho_last_error": (ctypes.c_char_p, []),
@@ -349,6 +351,27 @@ def ptycho_tile_accumulate(ctx: Context, tile_grad, box, grad) -> None:
     ctx._bind_stream()
     _check(lib().ptycho_tile_accumulate(ctx.handle, c_vp(tile_grad.data_ptr()), ey0, ex0, eh, ew, H, W,
                                         c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1)))
+
+
+EXCHANGE_ADD, EXCHANGE_REPLACE = 0, 1
+
+
+def ptycho_box_exchange(ctx: Context, src, src_origin, dst, dst_origin, replace: bool = False) -> None:
+    """On the overlap of two boxes (global origins (y0, x0), sizes from the
+    tensors' shapes): dst += src, or dst = src with replace=True.  src and dst
+    are complex64 [S, h, w] views with unit stride along w, in separate memory."""
+    torch = _torch()
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64:
+            raise ValueError(f"{name} must be a complex64 CUDA tensor")
+        if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != ctx.S:
+            raise ValueError(f"{name} must be [S, h, w] with unit stride along w")
+    ctx._bind_stream()
+    _check(lib().ptycho_box_exchange(ctx.handle, ctx.S, c_vp(src.data_ptr()), int(src_origin[0]),
+                                     int(src_origin[1]), src.shape[1], src.shape[2], src.stride(0), src.stride(1),
+                                     c_vp(dst.data_ptr()), int(dst_origin[0]), int(dst_origin[1]), dst.shape[1],
+                                     dst.shape[2], dst.stride(0), dst.stride(1),
+                                     EXCHANGE_REPLACE if replace else EXCHANGE_ADD))
 
 
 def ptycho_zero_gradient(ctx: Context, grad) -> None:

@@ -3,7 +3,10 @@
 // launches of the fused kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <utility>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -390,6 +393,38 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
   float2* g = static_cast<float2*>(grad) + static_cast<int64_t>(ey0) * grad_ld + ex0;
   PT_HIP(ptycho::launch_tile_accumulate(static_cast<const float2*>(tile_grad), ctx->S, eh, ew, g, grad_slice_stride,
                                         grad_ld, ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_box_exchange(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
+                        int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0,
+                        int32_t dh, int32_t dw, int64_t d_slice_stride, int32_t d_ld, uint32_t mode) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (!src || !dst) return fail(PTYCHO_E_ARG, "null buffer");
+  if (mode != PTYCHO_EXCHANGE_ADD && mode != PTYCHO_EXCHANGE_REPLACE) return fail(PTYCHO_E_ARG, "bad mode %u", mode);
+  if (S < 1 || S > 65535) return fail(PTYCHO_E_ARG, "slice count %d outside [1, 65535]", S);
+  if (sh < 0 || sw < 0 || dh < 0 || dw < 0) return fail(PTYCHO_E_SHAPE, "negative box size");
+  if (s_ld < sw || d_ld < dw || (S > 1 && (s_slice_stride < static_cast<int64_t>(sh) * s_ld ||
+                                           d_slice_stride < static_cast<int64_t>(dh) * d_ld)))
+    return fail(PTYCHO_E_SHAPE, "buffer strides do not cover their boxes");
+  const int32_t oy0 = sy0 > dy0 ? sy0 : dy0, ox0 = sx0 > dx0 ? sx0 : dx0;
+  const int64_t oy1 = std::min<int64_t>(static_cast<int64_t>(sy0) + sh, static_cast<int64_t>(dy0) + dh);
+  const int64_t ox1 = std::min<int64_t>(static_cast<int64_t>(sx0) + sw, static_cast<int64_t>(dx0) + dw);
+  // address ranges [first, last element + 1) of the two buffers
+  auto span = [&](const void* p, int32_t h, int32_t w, int64_t ss, int32_t ld) {
+    const int64_t last = (h > 0 && w > 0) ? (static_cast<int64_t>(S - 1) * (S > 1 ? ss : 0) +
+                                             static_cast<int64_t>(h - 1) * ld + w) : 0;
+    const uintptr_t b = reinterpret_cast<uintptr_t>(p);
+    return std::make_pair(b, b + static_cast<uintptr_t>(last) * sizeof(float2));
+  };
+  const auto a = span(src, sh, sw, s_slice_stride, s_ld), b = span(dst, dh, dw, d_slice_stride, d_ld);
+  if (a.first < b.second && b.first < a.second) return fail(PTYCHO_E_ARG, "source and destination share memory");
+  if (oy0 >= oy1 || ox0 >= ox1) return PTYCHO_OK;  // no overlap
+  const int oh = static_cast<int>(oy1 - oy0), ow = static_cast<int>(ox1 - ox0);
+  const float2* sp = static_cast<const float2*>(src) + static_cast<int64_t>(oy0 - sy0) * s_ld + (ox0 - sx0);
+  float2* dp = static_cast<float2*>(dst) + static_cast<int64_t>(oy0 - dy0) * d_ld + (ox0 - dx0);
+  PT_HIP(ptycho::launch_box_exchange(sp, s_slice_stride, s_ld, dp, d_slice_stride, d_ld, S, oh, ow,
+                                     mode == PTYCHO_EXCHANGE_REPLACE, ctx->stream));
   return PTYCHO_OK;
 }
 

@@ -216,3 +216,118 @@ class StreamingTileWalk:
             B.ptycho_tile_accumulate(self.ctx, tg, (0, 0, eh, ew), gb)
             grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew].copy_(gb)
         return d["loss"]
+
+
+class DecomposedTileWalk:
+    """The decomposition's per-device data flow on one GPU (Section V, Alg. 1).
+
+    Every tile keeps its own accumulated-gradient buffer on its extended box,
+    as each device of the paper's mesh does.  ``step`` computes every tile's
+    gradient into its buffer (tile launches alternate between two lanes, as in
+    the resident walk), then ``passes`` runs the four directional passes as
+    exchanges between the buffers (``ptycho_box_exchange``): down each tile
+    column add, up each column replace, along each tile row add, back along
+    each row replace.  Afterwards every buffer holds the summed gradient of all
+    tiles on its box -- what each device needs for its own update -- also
+    where tiles two apart overlap (tile < 2 halo), which a single exchange with
+    the direct neighbours does not cover.  ``stitch`` copies the tiles'
+    interiors into one array (the final stitch of Alg. 1).  The buffers take
+    the sum of all extended boxes, the memory of the whole device mesh.
+    """
+
+    def __init__(self, ctx: B.Context, plan: TileWalk, device="cuda:0", lanes: int = 2):
+        import torch
+        self.ctx, self.plan = ctx, plan
+        S = ctx.S
+        lanes = max(1, int(lanes))
+        self.ctxs = [ctx] + [B.Context(ctx.M, ctx.S, *ctx.physics, max_positions=max(plan.max_count, 1))
+                             for _ in range(lanes - 1)]
+        for c in self.ctxs:
+            c.reserve(max(plan.max_count, 1))
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
+        self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
+        self.bufs = [torch.empty((S, p.box[2], p.box[3]), dtype=torch.complex64, device=device)
+                     for p in plan.plans]
+        self.tile_loss = torch.zeros(len(plan.plans), dtype=torch.float64, device=device)
+
+    def device_bytes(self) -> int:
+        return sum(b.numel() * b.element_size() for b in self.bufs)
+
+    def check(self) -> int:
+        st = 0
+        for c in self.ctxs:
+            st |= c.check()
+        return st
+
+    def tile_gradients(self, obj, probe, meas_sorted):
+        """Every tile's own gradient into its buffer (no exchange yet); returns the per-tile losses."""
+        import torch
+        cur = torch.cuda.current_stream()
+        start = torch.cuda.Event()
+        start.record(cur)
+        for s in self.streams:
+            s.wait_event(start)
+        for k, p in enumerate(self.plan.plans):
+            lane = k % len(self.ctxs)
+            ey0, ex0, eh, ew = p.box
+            with torch.cuda.stream(self.streams[lane]):
+                B.ptycho_tile_grad(self.ctxs[lane], obj[:, ey0:ey0 + eh, ex0:ex0 + ew], p.box, p.tile,
+                                   self.plan.halo, self.plan.H, self.plan.W, probe, self.pos[p.lo:p.hi],
+                                   meas_sorted[p.lo:p.hi], tile_grad=self.bufs[k], loss=self.tile_loss[k:k + 1])
+        for s in self.streams:
+            cur.wait_stream(s)
+        return self.tile_loss
+
+    def _exchange(self, src: int, dst: int, replace: bool) -> None:
+        a, b = self.plan.plans[src].box, self.plan.plans[dst].box
+        B.ptycho_box_exchange(self.ctx, self.bufs[src], (a[0], a[1]), self.bufs[dst], (b[0], b[1]), replace)
+
+    def passes(self) -> None:
+        """Vertical forward (add) and backward (replace), then horizontal forward and backward."""
+        ty_n, tx_n = self.plan.tiles
+        for tx in range(tx_n):
+            for ty in range(ty_n - 1):
+                self._exchange(ty * tx_n + tx, (ty + 1) * tx_n + tx, replace=False)
+        for tx in range(tx_n):
+            for ty in range(ty_n - 1, 0, -1):
+                self._exchange(ty * tx_n + tx, (ty - 1) * tx_n + tx, replace=True)
+        for ty in range(ty_n):
+            for tx in range(tx_n - 1):
+                self._exchange(ty * tx_n + tx, ty * tx_n + tx + 1, replace=False)
+        for ty in range(ty_n):
+            for tx in range(tx_n - 1, 0, -1):
+                self._exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
+
+    def pass_bytes(self) -> int:
+        """HBM bytes the passes move: overlap x S x 8 B, read twice and written once per add, read and
+        written once per replace."""
+        ty_n, tx_n = self.plan.tiles
+        S = self.ctx.S
+        total = 0
+
+        def ov(i, j):
+            a, b = self.plan.plans[i].box, self.plan.plans[j].box
+            h = min(a[0] + a[2], b[0] + b[2]) - max(a[0], b[0])
+            w = min(a[1] + a[3], b[1] + b[3]) - max(a[1], b[1])
+            return max(h, 0) * max(w, 0)
+        for tx in range(tx_n):
+            for ty in range(ty_n - 1):
+                total += 3 * ov(ty * tx_n + tx, (ty + 1) * tx_n + tx) + 2 * ov((ty + 1) * tx_n + tx, ty * tx_n + tx)
+        for ty in range(ty_n):
+            for tx in range(tx_n - 1):
+                total += 3 * ov(ty * tx_n + tx, ty * tx_n + tx + 1) + 2 * ov(ty * tx_n + tx + 1, ty * tx_n + tx)
+        return total * S * 8
+
+    def step(self, obj, probe, meas_sorted):
+        """Tile gradients, then the passes; returns the per-tile losses."""
+        loss = self.tile_gradients(obj, probe, meas_sorted)
+        self.passes()
+        return loss
+
+    def stitch(self, out) -> None:
+        """out[:, tile] = buffer interior, for every tile (out: complex64 [S, H, W])."""
+        for k, p in enumerate(self.plan.plans):
+            ty0, ty1, tx0, tx1 = p.tile
+            ey0, ex0, _, _ = p.box
+            inner = self.bufs[k][:, ty0 - ey0:ty1 - ey0, tx0 - ex0:tx1 - ex0]
+            B.ptycho_box_exchange(self.ctx, inner, (ty0, tx0), out, (0, 0), replace=True)

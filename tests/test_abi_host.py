@@ -122,3 +122,11 @@ def test_batch_descriptor_layout_and_host_validation():
     assert L.ptycho_batch_create(ctypes.byref(h), arr, -1, 4) == -1
     assert not h.value
     assert L.ptycho_batch_step(None) == -1 and L.ptycho_batch_destroy(None) == 0
+
+
+def test_box_exchange_rejects_a_null_context():
+    import ctypes
+    from paper_2205_06327_amd import _binding as B
+    rc = B.lib().ptycho_box_exchange(None, 1, ctypes.c_void_p(8), 0, 0, 1, 1, 1, 1, ctypes.c_void_p(16), 0, 0, 1, 1,
+                                     1, 1, 0)
+    assert rc == -1 and b"null context" in B.lib().ptycho_last_error()
