@@ -530,6 +530,8 @@ struct ptycho_batch {
     int M = 0, item0 = 0, nitems = 0, smax = 1, grid = 0, grid_default = 0, ws_grid = 0;
     float2* ws = nullptr;
   } cls[2];                  // [0] M = 64, [1] M = 128
+  int* d_bounds = nullptr;   // per class: 9 item indices splitting its items into 8 parts of equal cost
+  int* d_next = nullptr;     // per class: 8 queue counters
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -541,7 +543,7 @@ void free_batch(ptycho_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   void* ptrs[] = {b->d_recs, b->d_items, b->d_item_loss, b->d_losses, b->d_hist, b->d_iter, b->d_h,
-                  b->d_tw64, b->d_tw128, b->d_status, b->cls[0].ws, b->cls[1].ws};
+                  b->d_tw64, b->d_tw128, b->d_status, b->cls[0].ws, b->cls[1].ws, b->d_bounds, b->d_next};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (b->stream) (void)hipStreamDestroy(b->stream);
@@ -571,6 +573,10 @@ int batch_enqueue_loss_grad(ptycho_batch* b, double* losses) {
     a.ws = c.ws;
     a.item_loss = b->d_item_loss;
     a.status = b->d_status;
+    const int ci = c.M == 64 ? 0 : 1;
+    a.bounds = b->d_bounds + 9 * ci;
+    a.next = b->d_next + 8 * ci;
+    PT_HIP(ptycho::launch_copy_ints(a.bounds, a.next, 8, b->stream));  // reset the queues (a kernel node)
     PT_HIP(ptycho::launch_batch(a, c.M, c.grid, b->stream));
   }
   PT_HIP(ptycho::launch_batch_finalize(b->d_recs, b->d_item_loss, losses ? losses : b->d_losses, b->d_hist, b->d_iter,
@@ -624,6 +630,7 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
   }
   // work list grouped by window size, then reconstruction, then position
   std::vector<ptycho::BatchRecon> recs(nrecon);
+  std::vector<int> bounds(18, 0);
   std::vector<int> items;
   items.reserve(2 * total_items);
   std::vector<float2> htab(static_cast<size_t>(nrecon) * 128);
@@ -661,6 +668,19 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
       if (R.S > c.smax) c.smax = R.S;
     }
     c.nitems = static_cast<int>(items.size() / 2) - c.item0;
+    // 8 contiguous parts of equal cost, one per XCD queue: an item costs 4S - 2 transforms
+    {
+      double total = 0.0;
+      for (int k = 0; k < c.nitems; ++k) total += 4.0 * recons[items[2 * (c.item0 + k)]].S - 2.0;
+      double acc = 0.0;
+      int x = 1;
+      bounds[9 * ci] = 0;
+      for (int k = 0; k < c.nitems && x < 8; ++k) {
+        acc += 4.0 * recons[items[2 * (c.item0 + k)]].S - 2.0;
+        while (x < 8 && acc >= total * x / 8.0) bounds[9 * ci + x++] = k + 1;
+      }
+      while (x <= 8) bounds[9 * ci + x++] = c.nitems;
+    }
     c.grid_default = b->num_cu * (c.M == 64 ? 2 : 1);
     c.ws_grid = c.grid_default * 2;  // the autotuner may pick up to twice the default
     c.grid = c.nitems < c.grid_default ? c.nitems : c.grid_default;
@@ -679,7 +699,9 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
             alloc(reinterpret_cast<void**>(&b->d_h), htab.size() * sizeof(float2)) &&
             alloc(reinterpret_cast<void**>(&b->d_tw64), 64 * sizeof(float2)) &&
             alloc(reinterpret_cast<void**>(&b->d_tw128), 128 * sizeof(float2)) &&
-            alloc(reinterpret_cast<void**>(&b->d_status), sizeof(unsigned));
+            alloc(reinterpret_cast<void**>(&b->d_status), sizeof(unsigned)) &&
+            alloc(reinterpret_cast<void**>(&b->d_bounds), bounds.size() * sizeof(int)) &&
+            alloc(reinterpret_cast<void**>(&b->d_next), 16 * sizeof(int));
   for (auto& c : b->cls)
     ok = ok && (c.nitems == 0 || c.smax < 2 ||
                 alloc(reinterpret_cast<void**>(&c.ws),
@@ -701,6 +723,7 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
       (e = hipMemcpy(b->d_tw64, tw64.data(), 64 * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->d_tw128, tw128.data(), 128 * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->d_iter, &zero, sizeof zero, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_bounds, bounds.data(), bounds.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(b->d_status, &uzero, sizeof uzero, hipMemcpyHostToDevice)) != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "batch upload");

@@ -58,6 +58,13 @@ struct BatchArgs {
   float2* ws;            // grid * (smax-1) * M*M
   double* item_loss;     // one per item of the whole list
   unsigned* status;
+  // Work queues: items [bounds[x], bounds[x+1]) of this launch (relative to
+  // item0) are served to the workgroups of XCD x through the counter next[x]
+  // (reset to bounds[x] before the launch).  The bounds split the items into
+  // 8 parts of equal cost ((4S - 2) transforms per item); with fewer than 8
+  // workgroups everything is in part 0.
+  const int* bounds;     // [9]
+  int* next;             // [8]
 };
 
 hipError_t launch_fused(const KernelArgs& a, int mode, int grid, hipStream_t st);
@@ -66,6 +73,7 @@ hipError_t launch_batch_finalize(const BatchRecon* recs, const double* item_loss
                                  const int* iter, int hist_rows, int nrecon, hipStream_t st);
 hipError_t launch_batch_elementwise(const BatchRecon* recs, int nrecon, int mode, int* iter, hipStream_t st);
 hipError_t launch_set_int(int* p, int v, hipStream_t st);
+hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);

@@ -482,6 +482,7 @@ template <int M>
 __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
   using G = Geo<M>;
   __shared__ Shared<G> sh;
+  __shared__ int job;
   const Lanes<G> L;
   float2 twb[G::X1];
   load_twb<G>(twb, a.tw, L.m2);
@@ -489,9 +490,15 @@ __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
   int cur = -1;
   float2 hy = make_float2(0.f, 0.f);
   PositionJob jb;
-  for (int j = 0;; ++j) {
-    const int k = job_position(j, a.nitems, static_cast<int>(gridDim.x));
-    if (k < 0) break;
+  // this workgroup's queue: blocks are dispatched round-robin over the 8 XCDs
+  const int x = gridDim.x >= 8 ? static_cast<int>(blockIdx.x & 7) : 0;
+  const int end = gridDim.x >= 8 ? a.bounds[x + 1] : a.bounds[8];  // parts are contiguous
+  for (;;) {
+    __syncthreads();  // every lane has read the previous job index
+    if (threadIdx.x == 0) job = atomicAdd(&a.next[x], 1);
+    __syncthreads();
+    const int k = job;
+    if (k >= end) break;
     const int item = a.item0 + k;
     const int r = a.items[2 * item];
     const int p = a.items[2 * item + 1];
@@ -524,6 +531,11 @@ __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
     const double f = run_position<G, kModeLossGrad>(jb, sh, twb, hy, ws, L);
     if (L.tid == 0) a.item_loss[item] = f;
   }
+}
+
+__global__ void copy_ints_kernel(const int* __restrict__ src, int* __restrict__ dst, int n) {
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) dst[i] = src[i];
 }
 
 // losses[r] = sum of the item losses of reconstruction r in item order; also
@@ -735,6 +747,11 @@ hipError_t launch_box_exchange(const float2* src, long long sslice, long long sl
   const unsigned rows = static_cast<unsigned>(oh < 1024 ? oh : 1024);
   hipLaunchKernelGGL(box_exchange_kernel, dim3(rows, static_cast<unsigned>(S)), dim3(256), 0, st, src, sslice, sld,
                      dst, dslice, dld, oh, ow, replace ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_ints_kernel, dim3(static_cast<unsigned>((n + 63) / 64)), dim3(64), 0, st, src, dst, n);
   return hipGetLastError();
 }
 
