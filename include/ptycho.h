@@ -235,9 +235,13 @@ int ptycho_profile_read(ptycho_ctx* ctx, double* total_ms, int64_t* launches, in
  * Batched reconstructions.  Many independent problems of uneven size (object,
  * slice count, scan, window size 64 or 128, dose) are served by one persistent
  * launch per window size that walks a work list of (reconstruction, position)
- * items; one full-batch gradient-descent iteration t <- t - alpha * dF/dt
- * (Section II-B, last paragraph of the formulation; the tile update of Alg. 1)
- * can be recorded once in a hipGraph and replayed.
+ * items; the two window sizes' launches run side by side (the batch stream
+ * and a second stream of the batch, joined by events), and each launch's
+ * items are split into 8 parts of equal cost ((4S - 2) transforms per item),
+ * one per XCD, served to its workgroups through a device counter.  One
+ * full-batch gradient-descent iteration t <- t - alpha * dF/dt (Section II-B,
+ * last paragraph of the formulation; the tile update of Alg. 1) can be
+ * recorded once in a hipGraph and replayed.
  */
 typedef struct ptycho_recon {
   int32_t M;              /* window side, 64 or 128 */

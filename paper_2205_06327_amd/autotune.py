@@ -2,11 +2,13 @@
 
 For every window-size class of a batch the persistent launch can use a
 different number of workgroups (the register and LDS budget allows one
-128-window workgroup per CU, and up to three 64-window workgroups).  The tuner
-times one full loss/gradient pass of the batch for each candidate with HIP
-events on the batch stream, keeps the fastest, and caches the choice in a JSON
-file keyed by the device and the batch's shape signature, so later runs of the
-same shape skip the search.
+128-window workgroup per CU, and up to three 64-window workgroups).  The two
+classes run side by side on two streams, so the tuner times one full
+loss/gradient pass of the batch for every pair of candidates with HIP events
+on the batch stream, keeps the fastest, and caches the choice in a JSON file
+keyed by the device and the batch's shape signature, so later runs of the same
+shape skip the search.  A class with no reconstruction keeps grid 0 (the
+default).
 """
 from __future__ import annotations
 
@@ -59,17 +61,21 @@ def tune(batch: Batch, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
         for M in (64, 128):
             batch.set_grid(M, int(choice[str(M)]))
         return {64: int(choice["64"]), 128: int(choice["128"]), "ms": choice["ms"], "cached": True}
-    ms_in = {64: [cus, 2 * cus, 3 * cus], 128: [cus // 2, cus]}
-    best = {}
+    # the two window sizes run side by side, so their workgroup counts are tuned jointly
+    cand = {64: [cus, 2 * cus, 3 * cus], 128: [cus // 2, cus]}
+    present = {M: any(r.probe.shape[0] == M for r in batch.recons) for M in (64, 128)}
     for M in (64, 128):
-        timings = []
-        for g in ms_in[M]:
-            g = max(1, min(g, 2 * cus * (2 if M == 64 else 1)))
-            batch.set_grid(M, g)
-            timings.append((_time_pass(batch, reps), g))
-        t, g = min(timings)
-        batch.set_grid(M, g)
-        best[M] = g
+        cand[M] = sorted({max(1, min(g, 2 * cus * (2 if M == 64 else 1))) for g in cand[M]}) if present[M] else [0]
+    timings = []
+    for g64 in cand[64]:
+        for g128 in cand[128]:
+            batch.set_grid(64, g64)
+            batch.set_grid(128, g128)
+            timings.append((_time_pass(batch, reps), g64, g128))
+    _, g64, g128 = min(timings)
+    best = {64: g64, 128: g128}
+    for M in (64, 128):
+        batch.set_grid(M, best[M])
     t_best = _time_pass(batch, reps)
     result = {"64": best[64], "128": best[128], "ms": t_best}
     if cache_path:

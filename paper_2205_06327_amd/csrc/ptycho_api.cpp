@@ -530,6 +530,8 @@ struct ptycho_batch {
     int M = 0, item0 = 0, nitems = 0, smax = 1, grid = 0, grid_default = 0, ws_grid = 0;
     float2* ws = nullptr;
   } cls[2];                  // [0] M = 64, [1] M = 128
+  hipStream_t side = nullptr;  // the 128-window launch runs here, beside the 64-window one
+  hipEvent_t fork = nullptr, join = nullptr;
   int* d_bounds = nullptr;   // per class: 9 item indices splitting its items into 8 parts of equal cost
   int* d_next = nullptr;     // per class: 8 queue counters
   hipGraph_t graph = nullptr;
@@ -546,6 +548,9 @@ void free_batch(ptycho_batch* b) {
                   b->d_tw64, b->d_tw128, b->d_status, b->cls[0].ws, b->cls[1].ws, b->d_bounds, b->d_next};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   if (b->stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }
@@ -561,8 +566,15 @@ std::vector<float2> twiddles(int M) {
 
 int batch_enqueue_loss_grad(ptycho_batch* b, double* losses) {
   PT_HIP(ptycho::launch_batch_elementwise(b->d_recs, b->nrecon, 0, nullptr, b->stream));
+  // the two window sizes run side by side (fork/join through events, also under graph capture)
+  const bool both = b->cls[0].nitems > 0 && b->cls[1].nitems > 0;
+  if (both) {
+    PT_HIP(hipEventRecord(b->fork, b->stream));
+    PT_HIP(hipStreamWaitEvent(b->side, b->fork, 0));
+  }
   for (auto& c : b->cls) {
     if (c.nitems == 0) continue;
+    hipStream_t st = (both && c.M == 128) ? b->side : b->stream;
     ptycho::BatchArgs a{};
     a.recs = b->d_recs;
     a.items = b->d_items;
@@ -576,8 +588,12 @@ int batch_enqueue_loss_grad(ptycho_batch* b, double* losses) {
     const int ci = c.M == 64 ? 0 : 1;
     a.bounds = b->d_bounds + 9 * ci;
     a.next = b->d_next + 8 * ci;
-    PT_HIP(ptycho::launch_copy_ints(a.bounds, a.next, 8, b->stream));  // reset the queues (a kernel node)
-    PT_HIP(ptycho::launch_batch(a, c.M, c.grid, b->stream));
+    PT_HIP(ptycho::launch_copy_ints(a.bounds, a.next, 8, st));  // reset the queues (a kernel node)
+    PT_HIP(ptycho::launch_batch(a, c.M, c.grid, st));
+  }
+  if (both) {
+    PT_HIP(hipEventRecord(b->join, b->side));
+    PT_HIP(hipStreamWaitEvent(b->stream, b->join, 0));
   }
   PT_HIP(ptycho::launch_batch_finalize(b->d_recs, b->d_item_loss, losses ? losses : b->d_losses, b->d_hist, b->d_iter,
                                        b->hist_rows, b->nrecon, b->stream));
@@ -624,7 +640,10 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
   int dev = 0;
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&b->num_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess ||
-      (e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
+      (e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess ||
+      (e = hipEventCreateWithFlags(&b->join, hipEventDisableTiming)) != hipSuccess) {
     free_batch(b);
     return hip_fail(e, "batch stream");
   }
