@@ -266,6 +266,8 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
   if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
     return fail(PTYCHO_E_SHAPE, "gradient strides do not cover %dx%d", H, W);
+  if (static_cast<int64_t>(grad_ld) * ctx->M >= (int64_t(1) << 31))
+    return fail(PTYCHO_E_SHAPE, "gradient row stride too large");  // window row offsets are 32-bit
   if (grad == obj) return fail(PTYCHO_E_ARG, "gradient aliases the object");
   ptycho::KernelArgs a = base_args(ctx);
   a.n = n;
