@@ -249,6 +249,8 @@ def main():
     ap.add_argument("--plain-positions", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=3072)
     ap.add_argument("--lanes", type=int, default=2, help="streams the resident tile walk alternates between")
+    ap.add_argument("--checkpoint", type=int, default=1,
+                    help="keep every k-th incident wave, recompute the others in the adjoint sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -297,6 +299,8 @@ def main():
 
     plan = TileWalk(inputs["pos"], W, W, M, spec.tiles, spec.halo)
     ctx = pt.Context(M, S, spec.wavelength_A, spec.dz_A, spec.pixel_A, max_positions=spec.n)
+    if args.checkpoint != 1:
+        ctx.set_checkpoint(args.checkpoint)
     probe = torch.tensor(inputs["probe"], dtype=torch.complex64, device=dev)
     pos_sorted = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=dev)
     obj_true = torch.tensor(inputs["obj_true"], dtype=torch.complex64, device=dev)
@@ -372,7 +376,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": spec.name, "positions": spec.n, "slices": S, "object": [W, W], "window": M,
-                   "tiles": list(spec.tiles), "halo": spec.halo, "step_px": spec.step, "dose": spec.dose},
+                   "tiles": list(spec.tiles), "halo": spec.halo, "step_px": spec.step, "dose": spec.dose,
+                   "wave_checkpoint_interval": args.checkpoint},
         "hbm_roofline_positions_per_s": round(hbm_roofline_pos, 1),
         "hbm_roofline_frac_of_step": round(value / hbm_roofline_pos, 4),
         "roofline": roofline,

@@ -98,6 +98,22 @@ int ptycho_destroy(ptycho_ctx* ctx);
 int ptycho_set_stream(ptycho_ctx* ctx, void* stream);
 /* Grow the context's per-call position capacity (allocates; not for hot loops). */
 int ptycho_reserve(ptycho_ctx* ctx, int32_t max_positions);
+/*
+ * ptycho_set_checkpoint: how the gradient call obtains the incident waves
+ * psi_s of its adjoint sweep (Eq. 2 needs psi_s at slice s, in reverse order).
+ * The call always recomputes them from the probe and the object (nothing is
+ * kept between calls); within a position, interval 1 (the default) parks every
+ * wave of the forward sweep in the context's store, and interval k > 1 parks
+ * only the wave entering every k-th slice plus the last segment's waves and
+ * recomputes each earlier segment's inner waves from its checkpoint during the
+ * adjoint sweep: ws_slots(S, k) instead of S - 1 slots of M*M complex per
+ * workgroup (S = 16, k = 4: 7 instead of 15), for (k - 1)/k of the forward
+ * transforms again.  Results equal those of interval 1 up to the order of the
+ * gradient atomics.  Reallocates the store (synchronising the context stream);
+ * E_ARG outside [1, 64].
+ */
+int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval);
+
 /* Device bytes owned by the context (tables + workspace). */
 int64_t ptycho_workspace_bytes(const ptycho_ctx* ctx);
 

@@ -37,7 +37,7 @@ EXPORTED = (
     "ptycho_loss", "ptycho_batch_create", "ptycho_batch_destroy", "ptycho_batch_set_grid", "ptycho_batch_get_grid",
     "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
-    "ptycho_batch_stream", "ptycho_box_exchange",
+    "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
 )
 
 
@@ -83,6 +83,7 @@ def lib() -> ctypes.CDLL:
                                                       c_i64, c_i32]),
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
+            "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_box_exchange": (ctypes.c_int, [c_vp, c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32,
                                                    c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_u32]),
             "ptycho_profile_read": (ctypes.c_int, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
@@ -178,6 +179,7 @@ class Context:
         self._h = c_vp()
         self.M, self.S = int(M), int(S)
         self.physics = (float(wavelength_A), float(dz_A), float(pixel_A))
+        self.checkpoint = 1
         _check(lib().ptycho_create(ctypes.byref(self._h), self.M, self.S, float(wavelength_A), float(dz_A),
                                    float(pixel_A), int(max_positions), c_vp(_stream_ptr())))
 
@@ -203,6 +205,11 @@ class Context:
 
     def reserve(self, max_positions: int) -> None:
         _check(lib().ptycho_reserve(self.handle, int(max_positions)))
+
+    def set_checkpoint(self, interval: int) -> None:
+        """Keep the incident wave of every interval-th slice and recompute the others in the adjoint sweep."""
+        _check(lib().ptycho_set_checkpoint(self.handle, int(interval)))
+        self.checkpoint = int(interval)
 
     def workspace_bytes(self) -> int:
         return int(lib().ptycho_workspace_bytes(self.handle))

@@ -57,7 +57,8 @@ struct ptycho_ctx {
   int capacity = 0;        // positions per call
   float2* d_tw = nullptr;  // W_M^e
   float2* d_h = nullptr;   // separable propagator factor
-  float2* d_ws = nullptr;  // incident-wave store, grid * (S-1) * M*M
+  float2* d_ws = nullptr;  // incident-wave store, grid * ws_slots(S, ck) * M*M
+  int ck = 1;              // checkpoint interval of the incident waves
   double* d_loss = nullptr;  // per-position losses [capacity]
   unsigned* d_status = nullptr;
   int64_t bytes = 0;
@@ -112,6 +113,7 @@ ptycho::KernelArgs base_args(const ptycho_ctx* c) {
   a.tw = c->d_tw;
   a.h = c->d_h;
   a.ws = c->d_ws;
+  a.ck = c->ck;
   a.loss_work = c->d_loss;
   a.status = c->d_status;
   return a;
@@ -184,7 +186,7 @@ int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, d
     const double ph = -kPi * wavelength_A * dz_A * f * f;
     h[e2] = make_float2(static_cast<float>(std::cos(ph)), static_cast<float>(std::sin(ph)));
   }
-  const size_t ws_elems = static_cast<size_t>(c->grid) * (S > 1 ? S - 1 : 0) * M * M;
+  const size_t ws_elems = static_cast<size_t>(c->grid) * ptycho::ws_slots(S, 1) * M * M;
   if ((e = hipMalloc(&c->d_tw, M * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&c->d_h, M * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&c->d_loss, static_cast<size_t>(c->capacity) * sizeof(double))) != hipSuccess ||
@@ -395,6 +397,28 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
   float2* g = static_cast<float2*>(grad) + static_cast<int64_t>(ey0) * grad_ld + ex0;
   PT_HIP(ptycho::launch_tile_accumulate(static_cast<const float2*>(tile_grad), ctx->S, eh, ew, g, grad_slice_stride,
                                         grad_ld, ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (interval < 1 || interval > 64) return fail(PTYCHO_E_ARG, "checkpoint interval %d outside [1, 64]", interval);
+  if (interval == ctx->ck) return PTYCHO_OK;
+  const size_t old_elems = static_cast<size_t>(ctx->grid) * ptycho::ws_slots(ctx->S, ctx->ck) * ctx->M * ctx->M;
+  const size_t new_elems = static_cast<size_t>(ctx->grid) * ptycho::ws_slots(ctx->S, interval) * ctx->M * ctx->M;
+  if (new_elems != old_elems) {
+    PT_HIP(hipStreamSynchronize(ctx->stream));  // launches in flight may still use the store
+    float2* ws = nullptr;
+    if (new_elems > 0) {
+      hipError_t e = hipMalloc(&ws, new_elems * sizeof(float2));
+      if (e != hipSuccess) return fail(PTYCHO_E_NOMEM, "wave store: %s", hipGetErrorString(e));
+    }
+    if (ctx->d_ws) PT_HIP(hipFree(ctx->d_ws));
+    ctx->d_ws = ws;
+    ctx->bytes += static_cast<int64_t>(new_elems) * static_cast<int64_t>(sizeof(float2)) -
+                  static_cast<int64_t>(old_elems) * static_cast<int64_t>(sizeof(float2));
+  }
+  ctx->ck = interval;
   return PTYCHO_OK;
 }
 
@@ -726,7 +750,7 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
   for (auto& c : b->cls)
     ok = ok && (c.nitems == 0 || c.smax < 2 ||
                 alloc(reinterpret_cast<void**>(&c.ws),
-                      static_cast<size_t>(c.ws_grid) * (c.smax - 1) * c.M * c.M * sizeof(float2)));
+                      static_cast<size_t>(c.ws_grid) * ptycho::ws_slots(c.smax, 1) * c.M * c.M * sizeof(float2)));
   if (!ok) {
     free_batch(b);
     return fail(PTYCHO_E_NOMEM, "batch allocation failed: %s", hipGetErrorString(e));

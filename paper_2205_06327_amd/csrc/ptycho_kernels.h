@@ -10,6 +10,16 @@ constexpr int kModeIntensity = 0;  // |Psi|^2
 constexpr int kModeLoss = 1;       // f_i only
 constexpr int kModeLossGrad = 2;   // f_i and the adjoint gradient
 
+// Wave-store slots (M*M complex each) per workgroup for S slices with the
+// incident waves checkpointed every ck slices: the checkpoints psi_ck,
+// psi_2ck, ..., psi_last (last = the first slice of the last segment), the
+// inner waves of one segment, and, when earlier segments are recomputed, one
+// slot for the adjoint wave.  ck = 1 keeps all S - 1 waves.
+__host__ __device__ constexpr int ws_slots(int S, int ck) {
+  return S <= 1 ? 0
+                : ((S - 1) / ck) + ((ck < S ? ck : S) - 1) + (((S - 1) / ck) > 0 && ck > 1 ? 1 : 0);
+}
+
 struct KernelArgs {
   int M, S, n;
   // object window source: element (s, y, x) at obj[s*slice_stride + y*ld + x], y, x local to the box
@@ -30,7 +40,8 @@ struct KernelArgs {
   double* loss_pos;      // nullable [n]
   float2* grad;          // gradient, element (s, y, x) at grad[s*gslice + y*gld + x] (box-local)
   long long gslice, gld;
-  float2* ws;            // per-block incident-wave store: grid * (S-1) * M*M
+  float2* ws;            // per-block incident-wave store: grid * ws_slots(S, ck) * M*M
+  int ck;                // checkpoint interval of the incident waves
   unsigned* status;
   const double* grad_scale;  // nullable device scalar multiplying the gradient
 };
@@ -55,7 +66,7 @@ struct BatchArgs {
   int item0, nitems;     // this launch's slice of the list (one window size)
   int smax;              // largest slice count in the slice
   const float2* tw;
-  float2* ws;            // grid * (smax-1) * M*M
+  float2* ws;            // grid * ws_slots(smax, 1) * M*M
   double* item_loss;     // one per item of the whole list
   unsigned* status;
   // Work queues: items [bounds[x], bounds[x+1]) of this launch (relative to

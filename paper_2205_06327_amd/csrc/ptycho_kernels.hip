@@ -289,6 +289,7 @@ struct PositionJob {
   float2* grad;          // gradient window origin, element (s, y, x) at grad[s*gslice + y*gld + x]
   long long gld, gslice;
   float gscale;          // 2 x the upstream gradient factor
+  int ck;                // checkpoint interval of the incident waves (1: all kept)
 };
 
 // Per-workgroup state shared by all positions a workgroup processes.
@@ -320,19 +321,34 @@ __device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* _
 // The staging costs an LDS round trip and two barriers per slice, which pays
 // off for 128-windows over many slices (the tile walk) but not for 64-windows
 // or the short slice stacks of the batched launch.
-template <class G, int MODE, bool LINES = false>
+template <class G, int MODE, bool LINES = false, bool CKPT = false>
 __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
                                                float2 hy, float2* __restrict__ ws, const Lanes<G>& L) {
   constexpr bool GRAD = MODE == kModeLossGrad;
   constexpr bool LOSS = MODE != kModeIntensity;
   const int S = jb.S;
+  // Incident waves for the adjoint sweep.  The slices are cut into segments of
+  // ck; the forward sweep keeps the wave entering every segment (a
+  // checkpoint, psi_ck, psi_2ck, ...) and every wave of the last segment; the
+  // adjoint sweep recomputes the inner waves of each earlier segment from its
+  // checkpoint just before sweeping it (ck = 1: every wave is kept, nothing is
+  // recomputed).  Slots: the checkpoints, then the inner waves of the segment
+  // being swept, then one slot holding the adjoint wave while a segment is
+  // recomputed (ws_slots(S, ck) in all).
+  const int ck = CKPT ? jb.ck : 1;  // without CKPT the segment logic folds away at compile time
+  const int last = ((S - 1) / ck) * ck;  // first slice of the last segment
+  const int nck = last / ck;
+  auto wave_slot = [&](int s, int seg) -> float2* {  // psi_s, s >= 1, of the segment starting at seg
+    const int k = s == seg ? s / ck - 1 : nck + (s - seg - 1);
+    return ws + static_cast<long long>(k + opaque_zero()) * (G::M * G::M);
+  };
   float2 v[G::R];
   float2 t[G::R];  // the next slice's transmission window, loaded one propagation ahead
   load_window<G>(v, jb.probe, G::M, L);
   load_window<G>(t, jb.win, jb.ld, L);
   for (int s = 0; s < S; ++s) {
-    if (GRAD && s >= 1) {
-      float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
+    if (GRAD && s >= 1 && (s % ck == 0 || s > last)) {
+      float2* __restrict__ w = wave_slot(s, s % ck == 0 ? s : last);
       sfor<G::R>([&](auto rc) { store_nt(&w[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -391,7 +407,8 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   idft2_c_to_a<G>(v, sh.lds, twb, L);  // chi_{S-1} = DFT^H g (its barriers make red[] visible)
   if (L.tid == 0)
     for (int w = 0; w < G::T / 64; ++w) f += sh.red[w];
-  for (int s = S - 1; s >= 0; --s) {
+  // One adjoint step at slice s with psi_s from the store (w) or the probe (s = 0).
+  auto adjoint_step = [&](int s, const float2* __restrict__ w) {
     // psi_s and the transmission window are loaded together and consumed
     // before the gradient atomics are issued: memory operations retire in
     // order, so loads issued behind the atomics would wait for them.  The
@@ -402,7 +419,6 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
     } else {
-      const float2* __restrict__ w = ws + static_cast<long long>(s - 1 + opaque_zero()) * (G::M * G::M);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
       load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
       __builtin_amdgcn_sched_barrier(0);
@@ -422,6 +438,36 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       scatter_add<G>(jb.grad + s * jb.gslice, jb.gld, g, L);
     }
     if (s > 0) propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
+  };
+  if constexpr (!CKPT) {
+    for (int s = S - 1; s >= 0; --s) adjoint_step(s, s > 0 ? wave_slot(s, s) : nullptr);
+  } else {
+    for (int seg = last; seg >= 0; seg -= ck) {
+      const int seg_end = seg + ck < S ? seg + ck : S;
+      if (seg < last && seg_end - seg > 1) {
+        // recompute psi_{seg+1 .. seg_end-1} from the checkpoint; the adjoint wave waits in its slot
+        float2* __restrict__ park = ws + static_cast<long long>(nck + (ck < S ? ck : S) - 1 + opaque_zero()) *
+                                             (G::M * G::M);
+        sfor<G::R>([&](auto rc) { store_nt(&park[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
+        if (seg == 0) {
+          load_window<G>(v, jb.probe, G::M, L);
+        } else {
+          const float2* __restrict__ w = wave_slot(seg, seg);
+          sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
+        }
+        for (int s = seg; s + 1 < seg_end; ++s) {
+          load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
+          __builtin_amdgcn_sched_barrier(0);
+          sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
+          propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
+          float2* __restrict__ w = wave_slot(s + 1, seg);
+          sfor<G::R>([&](auto rc) { store_nt(&w[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
+        }
+        const float2* __restrict__ pk = park + opaque_zero();
+        sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = load_nt(&pk[decltype(rc)::value * G::T + L.tid]); });
+      }
+      for (int s = seg_end - 1; s >= seg; --s) adjoint_step(s, s > 0 ? wave_slot(s, seg) : nullptr);
+    }
   }
   __syncthreads();  // red[] and lds reuse by the next position
   return f;
@@ -439,7 +485,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
   __syncthreads();
 
   const int S = a.S;
-  float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * (S > 1 ? S - 1 : 0) * (G::M * G::M);
+  float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * ws_slots(S, a.ck) * (G::M * G::M);
   PositionJob jb;
   jb.ld = a.ld;
   jb.sstride = a.slice_stride;
@@ -448,6 +494,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
   jb.gld = a.gld;
   jb.gslice = a.gslice;
   jb.gscale = 2.0f * (a.grad_scale != nullptr ? static_cast<float>(*a.grad_scale) : 1.0f);
+  jb.ck = a.ck;
 
   for (int j = 0;; ++j) {
     const int p = job_position(j, a.n, static_cast<int>(gridDim.x));
@@ -465,7 +512,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
     jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
     jb.grad = a.grad + static_cast<long long>(y0) * a.gld + x0;
-    const double f = run_position<G, MODE, G::M == 128>(jb, sh, twb, hy, ws, L);
+    const double f = run_position<G, MODE, G::M == 128, true>(jb, sh, twb, hy, ws, L);
     if (LOSS && L.tid == 0) {
       a.loss_work[p] = f;
       if (a.loss_pos != nullptr) a.loss_pos[p] = f;
@@ -486,7 +533,7 @@ __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
   const Lanes<G> L;
   float2 twb[G::X1];
   load_twb<G>(twb, a.tw, L.m2);
-  float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * (a.smax > 1 ? a.smax - 1 : 0) * (G::M * G::M);
+  float2* __restrict__ ws = a.ws + static_cast<long long>(blockIdx.x) * ws_slots(a.smax, 1) * (G::M * G::M);
   int cur = -1;
   float2 hy = make_float2(0.f, 0.f);
   PositionJob jb;
@@ -528,6 +575,7 @@ __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
     jb.gld = R.ld;
     jb.gslice = R.slice_stride;
     jb.gscale = 2.0f;
+    jb.ck = 1;
     const double f = run_position<G, kModeLossGrad>(jb, sh, twb, hy, ws, L);
     if (L.tid == 0) a.item_loss[item] = f;
   }

@@ -90,6 +90,8 @@ class ResidentTileWalk:
                              for _ in range(lanes - 1)]
         for c in self.ctxs:
             c.reserve(max(plan.max_count, 1))
+            if c.checkpoint != ctx.checkpoint:
+                c.set_checkpoint(ctx.checkpoint)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
         self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
         self.tile_bufs = [torch.empty((S, eh, ew), dtype=torch.complex64, device=device) for _ in range(lanes)]
@@ -244,6 +246,8 @@ class DecomposedTileWalk:
                              for _ in range(lanes - 1)]
         for c in self.ctxs:
             c.reserve(max(plan.max_count, 1))
+            if c.checkpoint != ctx.checkpoint:
+                c.set_checkpoint(ctx.checkpoint)
         self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
         self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
         self.bufs = [torch.empty((S, p.box[2], p.box[3]), dtype=torch.complex64, device=device)

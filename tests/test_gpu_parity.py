@@ -177,3 +177,33 @@ def test_device_side_window_checks(torch_cuda):
     assert e.value.name == "PTYCHO_E_BOUNDS"
     assert float(I[1].max()) == -1.0 and float(I[0].min()) >= 0.0
     assert ctx.check() == 0  # cleared
+
+
+def test_checkpointed_wave_recomputation(torch_cuda):
+    """Keeping only every k-th incident wave and recomputing the others in the adjoint sweep
+    gives the same losses (the forward sweep is unchanged) and the same gradient up to the
+    order of the gradient atomics, with a smaller wave store."""
+    import torch
+    import paper_2205_06327_amd as pt
+    spec = ps.with_overrides(ps.workload("ms16-2048-m128-tiles4x4"), W=256, ny=3, nx=4, step=14)
+    say("checkpoint intervals 1..5 and 16 on 16 slices, 12 positions")
+    d = problem(spec)
+    t = to_dev(d)
+    ctx = context(spec, spec.n)
+    G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+    results = {}
+    for k in (1, 2, 3, 4, 5, 16):
+        ctx.set_checkpoint(k)
+        lpp = torch.zeros(spec.n, dtype=torch.float64, device="cuda:0")
+        _, g = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], loss_per_pos=lpp)
+        assert ctx.check() == 0
+        torch.cuda.synchronize()
+        results[k] = (lpp.cpu().numpy(), g.cpu().numpy(), ctx.workspace_bytes())
+    l1, g1, b1 = results[1]
+    for k, (lk, gk, bk) in results.items():
+        np.testing.assert_array_equal(lk, l1)
+        assert rel_l2(gk, g1) <= 1e-6, k
+        assert rel_l2(gk, G_ref) <= 1e-4, k
+    assert results[4][2] < b1 and results[16][2] == b1
+    with pytest.raises(pt.PtychoError):
+        ctx.set_checkpoint(0)
