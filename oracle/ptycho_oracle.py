@@ -67,6 +67,7 @@ __all__ = [
     "gd_step_size",
     "neighbour_add",
     "directional_passes",
+    "alg1_tiles",
     "gd_step",
 ]
 
@@ -317,6 +318,59 @@ def directional_passes(tile_results: Sequence[Dict[str, object]], tiles: Tuple[i
         for tx in range(tx_n - 1, 0, -1):
             exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
     return acc
+
+
+def alg1_tiles(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray, H: np.ndarray,
+               tiles: Tuple[int, int], halo: int, step: float, batch: int, T: int, iterations: int
+               ) -> Tuple[List[float], np.ndarray]:
+    """Alg. 1 with one tile per device, read with mini-batches of positions.
+
+    Every tile holds its own extended copy V_k of the object and an
+    accumulation buffer AccBuf_k.  In every iteration each tile walks its own
+    positions in scan order, `batch` at a time (batch = 1 is the per-probe loop
+    of Alg. 1): the batch's gradient, evaluated at V_k, is added to AccBuf_k and
+    V_k takes the step V_k -= step * gradient.  After every T batches (the
+    delayed accumulation) and after the last batch of an iteration, the
+    directional passes run on the buffers, every tile takes
+    V_k -= step * AccBuf_k, and the buffers are cleared.  Returns the loss of
+    each iteration (each position's f_i evaluated when it is visited) and the
+    tiles' interiors stitched into one object."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    S, Hobj, Wobj = obj.shape
+    M = probe.shape[0]
+    ty_n, tx_n = tiles
+    owner = bin_positions(pos, Hobj, Wobj, M, ty_n, tx_n)
+    mine = [np.nonzero(owner == k)[0] for k in range(ty_n * tx_n)]
+    boxes = [extended_box(Hobj, Wobj, ty_n, tx_n, k // tx_n, k % tx_n, halo) for k in range(ty_n * tx_n)]
+    V = [obj[:, b[0]:b[1], b[2]:b[3]].copy() for b in boxes]
+    acc = [{"box": b, "grad": np.zeros_like(v)} for b, v in zip(boxes, V)]
+    steps = max((len(m) + batch - 1) // batch for m in mine)
+    losses = []
+    for _ in range(iterations):
+        total = 0.0
+        for j in range(steps):
+            for k, b in enumerate(boxes):
+                g = np.zeros_like(V[k])
+                for i in mine[k][j * batch:(j + 1) * batch]:
+                    y0, x0 = int(pos[i][0]) - b[0], int(pos[i][1]) - b[2]
+                    f_i, patches = position_loss_and_patch_gradients(V[k], probe, y0, x0, meas[i], H)
+                    total += f_i
+                    g[:, y0:y0 + M, x0:x0 + M] += patches
+                acc[k]["grad"] += g
+                V[k] -= step * g
+            if (j + 1) % T == 0 or j == steps - 1:
+                acc = directional_passes(acc, tiles)
+                for k in range(len(V)):
+                    V[k] -= step * acc[k]["grad"]
+                    acc[k]["grad"][...] = 0.0
+        losses.append(total)
+    out = np.empty_like(obj)
+    ey, ex = tile_bounds(Hobj, ty_n), tile_bounds(Wobj, tx_n)
+    for k, b in enumerate(boxes):
+        ty, tx = divmod(k, tx_n)
+        y0, y1, x0, x1 = ey[ty], ey[ty + 1], ex[tx], ex[tx + 1]
+        out[:, y0:y1, x0:x1] = V[k][:, y0 - b[0]:y1 - b[0], x0 - b[2]:x1 - b[2]]
+    return losses, out
 
 
 # ---------------------------------------------------------------------------

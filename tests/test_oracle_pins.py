@@ -386,3 +386,41 @@ def test_directional_passes_on_physical_tile_gradients():
     for a in acc:
         ey0, ey1, ex0, ex1 = a["box"]
         np.testing.assert_allclose(a["grad"], G[:, ey0:ey1, ex0:ex1], rtol=0, atol=1e-12 * np.abs(G).max())
+
+
+def _alg1_problem():
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=56, ny=5, nx=5, step=6, S=2, M=16, R=4.0, C=1.0,
+                             strength=0.3)
+    d = ps.build_inputs(spec, with_eval=True)
+    H = oracle.fresnel_propagator(spec.M, LAM, DZ, PIX)
+    meas = oracle.forward(d["obj_true"], d["probe"], d["pos"], H)
+    return spec, d, H, meas
+
+
+def test_alg1_single_tile_full_batch_is_gradient_descent_with_double_step():
+    # one tile holding every position, one batch per iteration: the per-batch step and the
+    # step with the (identical) accumulated buffer add up to one gradient step of 2 * step
+    spec, d, H, meas = _alg1_problem()
+    alpha = oracle.gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
+    losses, V = oracle.alg1_tiles(d["obj_eval"], d["probe"], d["pos"], meas, H, (1, 1), 8, alpha,
+                                  batch=len(d["pos"]), T=1, iterations=3)
+    t = d["obj_eval"].astype(np.complex128)
+    ref = []
+    for _ in range(3):
+        L, _, G = oracle.loss_and_gradient(t, d["probe"], d["pos"], meas, H)
+        ref.append(L)
+        t = oracle.gd_step(t, G, 2 * alpha)
+    np.testing.assert_allclose(losses, ref, rtol=1e-12)
+    np.testing.assert_allclose(V, t, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("batch,T", [(1, 1), (2, 3), (4, 100)])
+def test_alg1_tiles_descend(batch, T):
+    # 4 x 4 tiles of 14 px with an 8 px halo (tiles two apart overlap): the loss falls every
+    # iteration for per-probe updates, delayed accumulation and once-per-iteration passes
+    spec, d, H, meas = _alg1_problem()
+    alpha = 0.5 * oracle.gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
+    losses, V = oracle.alg1_tiles(d["obj_eval"], d["probe"], d["pos"], meas, H, (4, 4), 8, alpha,
+                                  batch=batch, T=T, iterations=4)
+    assert all(b < a for a, b in zip(losses, losses[1:]))
+    assert oracle.loss_and_gradient(V, d["probe"], d["pos"], meas, H)[0] < losses[0]
