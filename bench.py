@@ -237,6 +237,70 @@ def run_batch(args, cores):
     print(json.dumps(out), flush=True)
 
 
+def run_alg1(args, cores):
+    """Alg. 1 over 2 x 2 tiles of the 8-slice 1024^2 scan with delayed accumulation: the loss per
+    iteration when the passes run after every batch of positions, twice per iteration and once per
+    iteration (the three communication frequencies the paper compares), and the rate of the iteration."""
+    import numpy as np
+    import torch
+
+    import ptycho_synth as ps
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.batch import gd_step_size
+    from paper_2205_06327_amd.tilewalk import Alg1Walk, TileWalk
+
+    dev = torch.device("cuda:0")
+    spec = ps.with_overrides(ps.workload("ms8-1024-m128"), tiles=(2, 2), halo=64)
+    M, S, W = spec.M, spec.S, spec.W
+    log(f"generating {spec.name}: {S} x {W}^2, {spec.n} positions, 2 x 2 tiles")
+    inputs = ps.build_inputs(spec, workers=cores)
+    plan = TileWalk(inputs["pos"], W, W, M, spec.tiles, spec.halo)
+    ctx = pt.Context(M, S, spec.wavelength_A, spec.dz_A, spec.pixel_A, max_positions=spec.n)
+    probe = torch.tensor(inputs["probe"], dtype=torch.complex64, device=dev)
+    pos_sorted = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=dev)
+    I = pt.ptycho_forward(ctx, torch.tensor(inputs["obj_true"], dtype=torch.complex64, device=dev), probe, pos_sorted)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed)
+    meas = torch.poisson(I, generator=gen)
+    del I
+    obj0 = torch.tensor(inputs["obj_eval"], dtype=torch.complex64, device=dev)
+    alpha = 0.5 * gd_step_size(inputs["probe"], inputs["pos"], W, W, S)
+    batch = 64  # positions per tile per update: 16 updates per tile per iteration
+    iters = max(args.steps, 1)
+    counts = [p.hi - p.lo for p in plan.plans]
+    steps = max((c + batch - 1) // batch for c in counts)
+    curves, ms = {}, {}
+    for label, T in (("every batch", 1), ("twice per iteration", (steps + 1) // 2), ("once per iteration", steps)):
+        walk = Alg1Walk(ctx, plan, obj0, probe, meas, alpha, batch, T, device=dev)
+        for _ in range(args.warmup):  # warm-up on a copy of the start, then restart
+            walk.iteration()
+        walk = Alg1Walk(ctx, plan, obj0, probe, meas, alpha, batch, T, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = [walk.iteration() for _ in range(iters)]
+        torch.cuda.synchronize()
+        ms[label] = (time.perf_counter() - t0) * 1e3 / iters
+        assert walk.check() == 0
+        curves[label] = [float(v.item()) for v in losses]
+        log(f"T = {T} ({label}): {ms[label]:.2f} ms/iteration, loss {curves[label][0]:.4g} -> {curves[label][-1]:.4g}")
+    once = "once per iteration"
+    value = spec.n / (ms[once] / 1e3)
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": iters,
+        "warmup": args.warmup, "ms_per_step": round(ms[once], 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "alg1-ms8-1024-m128-tiles2x2", "positions": spec.n, "slices": S,
+                   "object": [W, W], "window": M, "tiles": [2, 2], "halo": spec.halo, "batch_per_tile": batch,
+                   "updates_per_tile_per_iteration": steps,
+                   "step": "one Alg. 1 iteration: every tile's positions in batches, tile updates, passes"},
+        "convergence": {label: {"T_batches": T, "loss_per_iteration": curves[label],
+                                "ms_per_iteration": round(ms[label], 3)}
+                        for label, T in (("every batch", 1), ("twice per iteration", (steps + 1) // 2),
+                                         ("once per iteration", steps))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +348,8 @@ def main():
     cores = max(1, min(16, cores_avail))
     if args.workload == "batch32-uneven":
         return run_batch(args, cores)
+    if args.workload == "alg1-convergence":
+        return run_alg1(args, cores)
     spec = ps.workload(args.workload)
     M, S, W = spec.M, spec.S, spec.W
     log(f"generating {spec.name}: {S} x {W}^2 object, {spec.n} positions, M={M} ({cores} workers)")

@@ -99,6 +99,16 @@ int ptycho_set_stream(ptycho_ctx* ctx, void* stream);
 /* Grow the context's per-call position capacity (allocates; not for hot loops). */
 int ptycho_reserve(ptycho_ctx* ctx, int32_t max_positions);
 /*
+ * ptycho_box_axpy: dst += alpha * src on the overlap of two boxes, with the
+ * same buffer conventions and checks as ptycho_box_exchange (E_ARG also for
+ * a non-finite alpha).  The tile-local updates of Alg. 1 use it:
+ * AccBuf_k += dF/dV_k (alpha = 1) and V_k -= step * dF/dV_k (alpha = -step).
+ */
+int ptycho_box_axpy(ptycho_ctx* ctx, int32_t S, float alpha, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
+                    int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0, int32_t dh,
+                    int32_t dw, int64_t d_slice_stride, int32_t d_ld);
+
+/*
  * ptycho_set_checkpoint: how the gradient call obtains the incident waves
  * psi_s of its adjoint sweep (Eq. 2 needs psi_s at slice s, in reverse order).
  * The call always recomputes them from the probe and the object (nothing is

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     ptycho_tile_grad,
     ptycho_zero_gradient,
     ptycho_box_exchange,
+    ptycho_box_axpy,
     tile_box,
     validate_positions,
     version,

@@ -38,6 +38,7 @@ EXPORTED = (
     "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
+    "ptycho_box_axpy",
 )
 
 
@@ -84,6 +85,8 @@ def lib() -> ctypes.CDLL:
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_box_axpy": (ctypes.c_int, [c_vp, c_i32, ctypes.c_float, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64,
+                                               c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_box_exchange": (ctypes.c_int, [c_vp, c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32,
                                                    c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_u32]),
             "ptycho_profile_read": (ctypes.c_int, [c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
@@ -379,6 +382,21 @@ def ptycho_box_exchange(ctx: Context, src, src_origin, dst, dst_origin, replace:
                                      c_vp(dst.data_ptr()), int(dst_origin[0]), int(dst_origin[1]), dst.shape[1],
                                      dst.shape[2], dst.stride(0), dst.stride(1),
                                      EXCHANGE_REPLACE if replace else EXCHANGE_ADD))
+
+
+def ptycho_box_axpy(ctx: Context, alpha: float, src, src_origin, dst, dst_origin) -> None:
+    """dst += alpha * src on the overlap of two boxes (same conventions as ptycho_box_exchange)."""
+    torch = _torch()
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64:
+            raise ValueError(f"{name} must be a complex64 CUDA tensor")
+        if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != ctx.S:
+            raise ValueError(f"{name} must be [S, h, w] with unit stride along w")
+    ctx._bind_stream()
+    _check(lib().ptycho_box_axpy(ctx.handle, ctx.S, float(alpha), c_vp(src.data_ptr()), int(src_origin[0]),
+                                 int(src_origin[1]), src.shape[1], src.shape[2], src.stride(0), src.stride(1),
+                                 c_vp(dst.data_ptr()), int(dst_origin[0]), int(dst_origin[1]), dst.shape[1],
+                                 dst.shape[2], dst.stride(0), dst.stride(1)))
 
 
 def ptycho_zero_gradient(ctx: Context, grad) -> None:

@@ -422,12 +422,13 @@ int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval) {
   return PTYCHO_OK;
 }
 
-int ptycho_box_exchange(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
-                        int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0,
-                        int32_t dh, int32_t dw, int64_t d_slice_stride, int32_t d_ld, uint32_t mode) {
+namespace {
+int box_combine(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_t sx0, int32_t sh, int32_t sw,
+                int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0, int32_t dh, int32_t dw,
+                int64_t d_slice_stride, int32_t d_ld, bool replace, float alpha) {
   if (!ctx) return fail(PTYCHO_E_ARG, "null context");
   if (!src || !dst) return fail(PTYCHO_E_ARG, "null buffer");
-  if (mode != PTYCHO_EXCHANGE_ADD && mode != PTYCHO_EXCHANGE_REPLACE) return fail(PTYCHO_E_ARG, "bad mode %u", mode);
+  if (!std::isfinite(alpha)) return fail(PTYCHO_E_ARG, "non-finite scale");
   if (S < 1 || S > 65535) return fail(PTYCHO_E_ARG, "slice count %d outside [1, 65535]", S);
   if (sh < 0 || sw < 0 || dh < 0 || dw < 0) return fail(PTYCHO_E_SHAPE, "negative box size");
   if (s_ld < sw || d_ld < dw || (S > 1 && (s_slice_stride < static_cast<int64_t>(sh) * s_ld ||
@@ -449,9 +450,25 @@ int ptycho_box_exchange(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0
   const int oh = static_cast<int>(oy1 - oy0), ow = static_cast<int>(ox1 - ox0);
   const float2* sp = static_cast<const float2*>(src) + static_cast<int64_t>(oy0 - sy0) * s_ld + (ox0 - sx0);
   float2* dp = static_cast<float2*>(dst) + static_cast<int64_t>(oy0 - dy0) * d_ld + (ox0 - dx0);
-  PT_HIP(ptycho::launch_box_exchange(sp, s_slice_stride, s_ld, dp, d_slice_stride, d_ld, S, oh, ow,
-                                     mode == PTYCHO_EXCHANGE_REPLACE, ctx->stream));
+  PT_HIP(ptycho::launch_box_exchange(sp, s_slice_stride, s_ld, dp, d_slice_stride, d_ld, S, oh, ow, replace, alpha,
+                                     ctx->stream));
   return PTYCHO_OK;
+}
+}  // namespace
+
+int ptycho_box_exchange(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
+                        int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0,
+                        int32_t dh, int32_t dw, int64_t d_slice_stride, int32_t d_ld, uint32_t mode) {
+  if (mode != PTYCHO_EXCHANGE_ADD && mode != PTYCHO_EXCHANGE_REPLACE) return fail(PTYCHO_E_ARG, "bad mode %u", mode);
+  return box_combine(ctx, S, src, sy0, sx0, sh, sw, s_slice_stride, s_ld, dst, dy0, dx0, dh, dw, d_slice_stride, d_ld,
+                     mode == PTYCHO_EXCHANGE_REPLACE, 1.0f);
+}
+
+int ptycho_box_axpy(ptycho_ctx* ctx, int32_t S, float alpha, const void* src, int32_t sy0, int32_t sx0, int32_t sh,
+                    int32_t sw, int64_t s_slice_stride, int32_t s_ld, void* dst, int32_t dy0, int32_t dx0, int32_t dh,
+                    int32_t dw, int64_t d_slice_stride, int32_t d_ld) {
+  return box_combine(ctx, S, src, sy0, sx0, sh, sw, s_slice_stride, s_ld, dst, dy0, dx0, dh, dw, d_slice_stride, d_ld,
+                     false, alpha);
 }
 
 int ptycho_zero_gradient(ptycho_ctx* ctx, void* grad, int32_t H, int32_t W, int64_t grad_slice_stride,

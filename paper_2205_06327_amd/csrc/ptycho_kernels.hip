@@ -686,13 +686,13 @@ __global__ void tile_accumulate_kernel(const float2* __restrict__ tile, int S, i
   }
 }
 
-// One exchange of the accumulation passes: dst (+)= src over an oh x ow region
-// of S slices (both pointers at the region's top-left).  Workgroups walk rows
+// One exchange of the accumulation passes: dst = src, or dst += alpha * src,
+// over an oh x ow region of S slices (both pointers at the region's top-left).  Workgroups walk rows
 // of one slice (blockIdx.y), threads walk columns: row segments are
 // contiguous, so loads and stores coalesce.
 __global__ void box_exchange_kernel(const float2* __restrict__ src, long long sslice, long long sld,
                                     float2* __restrict__ dst, long long dslice, long long dld, int oh, int ow,
-                                    int replace) {
+                                    int replace, float alpha) {
   const long long s = blockIdx.y;
   for (int y = blockIdx.x; y < oh; y += gridDim.x) {
     const float2* __restrict__ sp = src + s * sslice + y * sld;
@@ -703,7 +703,7 @@ __global__ void box_exchange_kernel(const float2* __restrict__ src, long long ss
         dp[x] = v;
       } else {
         const float2 d = dp[x];
-        dp[x] = make_float2(d.x + v.x, d.y + v.y);
+        dp[x] = make_float2(d.x + alpha * v.x, d.y + alpha * v.y);
       }
     }
   }
@@ -791,10 +791,10 @@ hipError_t launch_tile_accumulate(const float2* tile, int S, int eh, int ew, flo
 }
 
 hipError_t launch_box_exchange(const float2* src, long long sslice, long long sld, float2* dst, long long dslice,
-                               long long dld, int S, int oh, int ow, bool replace, hipStream_t st) {
+                               long long dld, int S, int oh, int ow, bool replace, float alpha, hipStream_t st) {
   const unsigned rows = static_cast<unsigned>(oh < 1024 ? oh : 1024);
   hipLaunchKernelGGL(box_exchange_kernel, dim3(rows, static_cast<unsigned>(S)), dim3(256), 0, st, src, sslice, sld,
-                     dst, dslice, dld, oh, ow, replace ? 1 : 0);
+                     dst, dslice, dld, oh, ow, replace ? 1 : 0, alpha);
   return hipGetLastError();
 }
 

@@ -220,6 +220,39 @@ class StreamingTileWalk:
         return d["loss"]
 
 
+def directional_passes(ctx: B.Context, plan: TileWalk, bufs) -> None:
+    """Section V's passes between per-tile buffers (bufs[k] holds tile k's extended box), enqueued
+    on the caller's current stream: down every tile column add, up every column replace, along
+    every tile row add, back along every row replace."""
+    ty_n, tx_n = plan.tiles
+
+    def exchange(src: int, dst: int, replace: bool) -> None:
+        a, b = plan.plans[src].box, plan.plans[dst].box
+        B.ptycho_box_exchange(ctx, bufs[src], (a[0], a[1]), bufs[dst], (b[0], b[1]), replace)
+
+    for tx in range(tx_n):
+        for ty in range(ty_n - 1):
+            exchange(ty * tx_n + tx, (ty + 1) * tx_n + tx, replace=False)
+    for tx in range(tx_n):
+        for ty in range(ty_n - 1, 0, -1):
+            exchange(ty * tx_n + tx, (ty - 1) * tx_n + tx, replace=True)
+    for ty in range(ty_n):
+        for tx in range(tx_n - 1):
+            exchange(ty * tx_n + tx, ty * tx_n + tx + 1, replace=False)
+    for ty in range(ty_n):
+        for tx in range(tx_n - 1, 0, -1):
+            exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
+
+
+def stitch_interiors(ctx: B.Context, plan: TileWalk, bufs, out) -> None:
+    """out[:, tile] = interior of bufs[k] for every tile k (Alg. 1's final stitch)."""
+    for k, p in enumerate(plan.plans):
+        ty0, ty1, tx0, tx1 = p.tile
+        ey0, ex0, _, _ = p.box
+        inner = bufs[k][:, ty0 - ey0:ty1 - ey0, tx0 - ex0:tx1 - ex0]
+        B.ptycho_box_exchange(ctx, inner, (ty0, tx0), out, (0, 0), replace=True)
+
+
 class DecomposedTileWalk:
     """The decomposition's per-device data flow on one GPU (Section V, Alg. 1).
 
@@ -282,25 +315,9 @@ class DecomposedTileWalk:
             cur.wait_stream(s)
         return self.tile_loss
 
-    def _exchange(self, src: int, dst: int, replace: bool) -> None:
-        a, b = self.plan.plans[src].box, self.plan.plans[dst].box
-        B.ptycho_box_exchange(self.ctx, self.bufs[src], (a[0], a[1]), self.bufs[dst], (b[0], b[1]), replace)
-
     def passes(self) -> None:
         """Vertical forward (add) and backward (replace), then horizontal forward and backward."""
-        ty_n, tx_n = self.plan.tiles
-        for tx in range(tx_n):
-            for ty in range(ty_n - 1):
-                self._exchange(ty * tx_n + tx, (ty + 1) * tx_n + tx, replace=False)
-        for tx in range(tx_n):
-            for ty in range(ty_n - 1, 0, -1):
-                self._exchange(ty * tx_n + tx, (ty - 1) * tx_n + tx, replace=True)
-        for ty in range(ty_n):
-            for tx in range(tx_n - 1):
-                self._exchange(ty * tx_n + tx, ty * tx_n + tx + 1, replace=False)
-        for ty in range(ty_n):
-            for tx in range(tx_n - 1, 0, -1):
-                self._exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
+        directional_passes(self.ctx, self.plan, self.bufs)
 
     def pass_bytes(self) -> int:
         """HBM bytes the passes move: overlap x S x 8 B, read twice and written once per add, read and
@@ -330,8 +347,98 @@ class DecomposedTileWalk:
 
     def stitch(self, out) -> None:
         """out[:, tile] = buffer interior, for every tile (out: complex64 [S, H, W])."""
+        stitch_interiors(self.ctx, self.plan, self.bufs, out)
+
+
+class Alg1Walk:
+    """Alg. 1 on one device: one tile per (virtual) device, mini-batch reading.
+
+    Every tile keeps its own extended copy V_k of the object and an
+    accumulation buffer AccBuf_k.  An iteration walks every tile's positions
+    in scan order, ``batch`` at a time: the batch's gradient at V_k
+    (ptycho_tile_grad) is added to AccBuf_k and V_k takes
+    V_k -= step * gradient (ptycho_box_axpy).  After every ``T`` batches and
+    after an iteration's last batch, the directional passes run on the
+    buffers, every tile takes V_k -= step * AccBuf_k, and the buffers are
+    cleared.  With batch = 1 this is the per-probe loop of Alg. 1; a batch of a
+    few hundred positions per tile keeps the GPU busy.  Tiles' launches
+    alternate between two lanes (contexts and streams); the passes and the
+    accumulated update run on the caller's stream after both lanes.
+    """
+
+    def __init__(self, ctx: B.Context, plan: TileWalk, obj, probe, meas_sorted, step: float, batch: int, T: int,
+                 device="cuda:0", lanes: int = 2):
+        import torch
+        self.ctx, self.plan = ctx, plan
+        self.probe, self.meas = probe, meas_sorted
+        self.step_size, self.batch, self.T = float(step), max(1, int(batch)), max(1, int(T))
+        S = ctx.S
+        lanes = max(1, int(lanes))
+        self.ctxs = [ctx] + [B.Context(ctx.M, ctx.S, *ctx.physics, max_positions=self.batch)
+                             for _ in range(lanes - 1)]
+        for c in self.ctxs:
+            c.reserve(self.batch)
+            if c.checkpoint != ctx.checkpoint:
+                c.set_checkpoint(ctx.checkpoint)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
+        self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
+        self.V = []
+        for p in plan.plans:
+            ey0, ex0, eh, ew = p.box
+            self.V.append(obj[:, ey0:ey0 + eh, ex0:ex0 + ew].contiguous())
+        self.acc = [torch.zeros_like(v) for v in self.V]
+        eh, ew = plan.max_box
+        self.gbuf = [torch.empty((S, eh, ew), dtype=torch.complex64, device=device) for _ in range(lanes)]
+        counts = [p.hi - p.lo for p in plan.plans]
+        self.steps = max((c + self.batch - 1) // self.batch for c in counts) if counts else 0
+        self.losses = torch.zeros((max(self.steps, 1), len(plan.plans)), dtype=torch.float64, device=device)
+
+    def check(self) -> int:
+        st = 0
+        for c in self.ctxs:
+            st |= c.check()
+        return st
+
+    def _flush(self) -> None:
+        directional_passes(self.ctx, self.plan, self.acc)
         for k, p in enumerate(self.plan.plans):
-            ty0, ty1, tx0, tx1 = p.tile
-            ey0, ex0, _, _ = p.box
-            inner = self.bufs[k][:, ty0 - ey0:ty1 - ey0, tx0 - ex0:tx1 - ex0]
-            B.ptycho_box_exchange(self.ctx, inner, (ty0, tx0), out, (0, 0), replace=True)
+            o = (p.box[0], p.box[1])
+            B.ptycho_box_axpy(self.ctx, -self.step_size, self.acc[k], o, self.V[k], o)
+            B.ptycho_zero_gradient(self.ctx, self.acc[k])
+
+    def iteration(self):
+        """One pass over every tile's positions; returns the iteration's loss (device float64 [1])."""
+        import torch
+        cur = torch.cuda.current_stream()
+        self.losses.zero_()
+        n_lanes = len(self.ctxs)
+        for j in range(self.steps):
+            ev = torch.cuda.Event()
+            ev.record(cur)
+            for s in self.streams:
+                s.wait_event(ev)
+            slot = 0
+            for k, p in enumerate(self.plan.plans):
+                lo = p.lo + j * self.batch
+                hi = min(p.hi, lo + self.batch)
+                if hi <= lo:
+                    continue
+                lane = slot % n_lanes
+                slot += 1
+                ey0, ex0, eh, ew = p.box
+                g = self.gbuf[lane].view(-1)[: self.ctx.S * eh * ew].view(self.ctx.S, eh, ew)
+                with torch.cuda.stream(self.streams[lane]):
+                    B.ptycho_tile_grad(self.ctxs[lane], self.V[k], p.box, p.tile, self.plan.halo, self.plan.H,
+                                       self.plan.W, self.probe, self.pos[lo:hi], self.meas[lo:hi], tile_grad=g,
+                                       loss=self.losses[j, k:k + 1])
+                    B.ptycho_box_axpy(self.ctxs[lane], 1.0, g, (ey0, ex0), self.acc[k], (ey0, ex0))
+                    B.ptycho_box_axpy(self.ctxs[lane], -self.step_size, g, (ey0, ex0), self.V[k], (ey0, ex0))
+            for s in self.streams:
+                cur.wait_stream(s)
+            if (j + 1) % self.T == 0 or j == self.steps - 1:
+                self._flush()
+        return self.losses.sum().reshape(1)
+
+    def stitch(self, out) -> None:
+        """out[:, tile] = interior of V_k for every tile: the reconstruction."""
+        stitch_interiors(self.ctx, self.plan, self.V, out)

@@ -186,3 +186,36 @@ def test_decomposed_walk_directional_passes(torch_cuda):
     walk.stitch(stitched)
     torch.cuda.synchronize()
     assert rel_l2(stitched.cpu().numpy(), g_h) <= 1e-6
+
+
+@pytest.mark.parametrize("batch,T", [(4, 1), (4, 3)])
+def test_alg1_walk_matches_oracle(torch_cuda, batch, T):
+    import torch
+    from paper_2205_06327_amd.batch import gd_step_size
+    from paper_2205_06327_amd.tilewalk import Alg1Walk, TileWalk
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=192, S=2, ny=17, nx=17, step=8, tiles=(4, 4), halo=32)
+    say(f"Alg. 1 walk, 4x4 tiles of 48 px, halo 32, batch {batch}, T {T}, 2 iterations")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    alpha = 0.5 * gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
+    meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
+    walk = Alg1Walk(ctx, plan, t["obj"], t["probe"], meas_sorted, alpha, batch, T)
+    losses = [float(walk.iteration().item()) for _ in range(2)]
+    assert walk.check() == 0
+    V = torch.empty_like(t["obj"])
+    walk.stitch(V)
+    torch.cuda.synchronize()
+    ref_l, ref_V = oracle.alg1_tiles(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"], spec.tiles, spec.halo,
+                                     alpha, batch, T, 2)
+    np.testing.assert_allclose(losses, ref_l, rtol=1e-4)
+    assert losses[1] < losses[0]
+    # the update V - V0 is small next to V (|t| ~ 1): every FP32 write of V_k rounds by up to
+    # 2^-24 |V|, so the update's relative error is bounded by 1e-4 plus the number of writes per
+    # pixel (a step per batch and per flush, two iterations) times 2^-24 ||V0|| / ||V - V0||
+    V0 = d["obj_eval"].astype(np.complex128)
+    dV = ref_V - V0
+    writes = 2 * (walk.steps + -(-walk.steps // T))
+    tol = 1e-4 + writes * 2.0 ** -24 * np.linalg.norm(V0) / np.linalg.norm(dV)
+    assert rel_l2(V.cpu().numpy() - V0, dV) <= tol
