@@ -13,6 +13,10 @@
  *   Section III (tiles + halos): the image gradient and the probe locations
  *       are divided into tiles; each tile is extended by a halo that covers its
  *       probe windows; tile gradients of overlapping regions are added.
+ *   Section V: with separately held tile buffers, directional forward (add)
+ *       and backward (replace) passes leave the summed gradient on every
+ *       tile's box (ptycho_box_exchange); Alg. 1 updates each tile with its
+ *       own and its accumulated gradients (ptycho_box_axpy).
  *
  * Model computed by this library (per position i with window top-left (y0, x0)):
  *   psi_0 = probe;  phi_s = psi_s * t_s[y0:y0+M, x0:x0+M]
@@ -33,8 +37,9 @@
  *
  * Ownership: the caller allocates and frees every array; the library keeps no
  * pointer beyond the call's stream work.  A context owns its device tables and
- * its workspace (allocated in ptycho_create / ptycho_reserve only), so the hot
- * calls allocate nothing and are stream-ordered and asynchronous.
+ * its workspace (allocated in ptycho_create, ptycho_reserve and
+ * ptycho_set_checkpoint only), so the hot calls allocate nothing and are
+ * stream-ordered and asynchronous.
  *
  * Errors: every call returns PTYCHO_OK (0) or a negative code; a call that
  * fails host validation enqueues nothing.  ptycho_last_error() returns a

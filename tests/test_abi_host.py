@@ -130,3 +130,13 @@ def test_box_exchange_rejects_a_null_context():
     rc = B.lib().ptycho_box_exchange(None, 1, ctypes.c_void_p(8), 0, 0, 1, 1, 1, 1, ctypes.c_void_p(16), 0, 0, 1, 1,
                                      1, 1, 0)
     assert rc == -1 and b"null context" in B.lib().ptycho_last_error()
+
+
+def test_new_entry_points_reject_a_null_context():
+    import ctypes
+    from paper_2205_06327_amd import _binding as B
+    L = B.lib()
+    assert L.ptycho_set_checkpoint(None, 4) == -1
+    assert L.ptycho_box_axpy(None, 1, ctypes.c_float(1.0), ctypes.c_void_p(8), 0, 0, 1, 1, 1, 1,
+                             ctypes.c_void_p(16), 0, 0, 1, 1, 1, 1) == -1
+    assert b"null context" in L.ptycho_last_error()
