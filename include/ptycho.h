@@ -114,6 +114,25 @@ int ptycho_box_axpy(ptycho_ctx* ctx, int32_t S, float alpha, const void* src, in
                     int32_t dw, int64_t d_slice_stride, int32_t d_ld);
 
 /*
+ * Real-potential parametrisation (Section II-B: V is the sample's scattering
+ * potential; the slices enter the model through their transmissions):
+ *   ptycho_potential_transmission:  t = exp(i sigma V)
+ *   ptycho_potential_gradient:      dF/dV = sigma * Im(conj(t) * G), with
+ *       G = dF/dRe t + i dF/dIm t the gradient of ptycho_loss_grad (the chain
+ *       rule through t = exp(i sigma V)).
+ * V and dF/dV are float32 [S][H][W] (ctx->S slices) with (slice_stride, ld)
+ * in floats; t and G complex64 likewise.  Device arrays owned by the caller;
+ * stream-ordered; E_ARG / E_SHAPE on null pointers, non-finite sigma or
+ * strides that do not cover H x W.
+ */
+int ptycho_potential_transmission(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma, const float* V,
+                                  int64_t v_slice_stride, int32_t v_ld, void* t, int64_t t_slice_stride,
+                                  int32_t t_ld);
+int ptycho_potential_gradient(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma, const void* t,
+                              int64_t t_slice_stride, int32_t t_ld, const void* grad_t, int64_t g_slice_stride,
+                              int32_t g_ld, float* grad_V, int64_t gv_slice_stride, int32_t gv_ld);
+
+/*
  * ptycho_set_checkpoint: how the gradient call obtains the incident waves
  * psi_s of its adjoint sweep (Eq. 2 needs psi_s at slice s, in reverse order).
  * The call always recomputes them from the probe and the object (nothing is

@@ -65,6 +65,8 @@ __all__ = [
     "tile_gradient",
     "stitch_tile_gradients",
     "gd_step_size",
+    "transmission_from_potential",
+    "potential_gradient",
     "neighbour_add",
     "directional_passes",
     "alg1_tiles",
@@ -241,6 +243,20 @@ def stitch_tile_gradients(shape: Sequence[int], tile_results: Sequence[Dict[str,
         ey0, ey1, ex0, ex1 = r["box"]
         out[:, ey0:ey1, ex0:ex1] += r["grad"]
     return out
+
+
+# ---------------------------------------------------------------------------
+# Real-potential parametrisation (Section II-B: V is the scattering potential;
+# each slice enters through its transmission t = exp(i sigma V)).
+# ---------------------------------------------------------------------------
+def transmission_from_potential(V: np.ndarray, sigma: float) -> np.ndarray:
+    return np.exp(1j * sigma * np.asarray(V, dtype=np.float64))
+
+
+def potential_gradient(t: np.ndarray, G: np.ndarray, sigma: float) -> np.ndarray:
+    """dF/dV from G = dF/dRe t + i dF/dIm t: with dRe t/dV = -sigma Im t and
+    dIm t/dV = sigma Re t, dF/dV = sigma (Re t Im G - Im t Re G) = sigma Im(conj(t) G)."""
+    return sigma * np.imag(np.conj(t) * G)
 
 
 # ---------------------------------------------------------------------------

@@ -16,6 +16,8 @@ from ._binding import (  # noqa: F401
     ptycho_zero_gradient,
     ptycho_box_exchange,
     ptycho_box_axpy,
+    ptycho_potential_gradient,
+    ptycho_potential_transmission,
     tile_box,
     validate_positions,
     version,

@@ -38,7 +38,7 @@ EXPORTED = (
     "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
-    "ptycho_box_axpy",
+    "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient",
 )
 
 
@@ -85,6 +85,10 @@ def lib() -> ctypes.CDLL:
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_potential_transmission": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
+                                                             c_vp, c_i64, c_i32]),
+            "ptycho_potential_gradient": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
+                                                         c_vp, c_i64, c_i32, c_vp, c_i64, c_i32]),
             "ptycho_box_axpy": (ctypes.c_int, [c_vp, c_i32, ctypes.c_float, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64,
                                                c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_box_exchange": (ctypes.c_int, [c_vp, c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32,
@@ -397,6 +401,48 @@ def ptycho_box_axpy(ctx: Context, alpha: float, src, src_origin, dst, dst_origin
                                  int(src_origin[1]), src.shape[1], src.shape[2], src.stride(0), src.stride(1),
                                  c_vp(dst.data_ptr()), int(dst_origin[0]), int(dst_origin[1]), dst.shape[1],
                                  dst.shape[2], dst.stride(0), dst.stride(1)))
+
+
+def _plane(t, dtype, S, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype:
+        raise ValueError(f"{name} must be a {dtype} CUDA tensor")
+    if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != S:
+        raise ValueError(f"{name} must be [S, H, W] with unit stride along W")
+
+
+def ptycho_potential_transmission(ctx: Context, V, sigma: float, t=None):
+    """t = exp(i sigma V) for a float32 [S, H, W] potential; returns complex64 [S, H, W]."""
+    torch = _torch()
+    _plane(V, torch.float32, ctx.S, "V")
+    if t is None:
+        t = torch.empty(tuple(V.shape), dtype=torch.complex64, device=V.device)
+    _plane(t, torch.complex64, ctx.S, "t")
+    if tuple(t.shape) != tuple(V.shape):
+        raise ValueError("t must have V's shape")
+    ctx._bind_stream()
+    _check(lib().ptycho_potential_transmission(ctx.handle, V.shape[1], V.shape[2], float(sigma), c_vp(V.data_ptr()),
+                                               V.stride(0), V.stride(1), c_vp(t.data_ptr()), t.stride(0),
+                                               t.stride(1)))
+    return t
+
+
+def ptycho_potential_gradient(ctx: Context, t, grad_t, sigma: float, grad_V=None):
+    """dF/dV = sigma Im(conj(t) grad_t) for t = exp(i sigma V); returns float32 [S, H, W]."""
+    torch = _torch()
+    _plane(t, torch.complex64, ctx.S, "t")
+    _plane(grad_t, torch.complex64, ctx.S, "grad_t")
+    if grad_V is None:
+        grad_V = torch.empty(tuple(t.shape), dtype=torch.float32, device=t.device)
+    _plane(grad_V, torch.float32, ctx.S, "grad_V")
+    if tuple(grad_t.shape) != tuple(t.shape) or tuple(grad_V.shape) != tuple(t.shape):
+        raise ValueError("t, grad_t and grad_V must have one shape")
+    ctx._bind_stream()
+    _check(lib().ptycho_potential_gradient(ctx.handle, t.shape[1], t.shape[2], float(sigma), c_vp(t.data_ptr()),
+                                           t.stride(0), t.stride(1), c_vp(grad_t.data_ptr()), grad_t.stride(0),
+                                           grad_t.stride(1), c_vp(grad_V.data_ptr()), grad_V.stride(0),
+                                           grad_V.stride(1)))
+    return grad_V
 
 
 def ptycho_zero_gradient(ctx: Context, grad) -> None:

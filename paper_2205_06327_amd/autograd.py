@@ -8,6 +8,11 @@ incident waves of that position only for the duration of its own adjoint
 sweep, and scatter-adds dF/dRe t + i dF/dIm t (Eq. 2) scaled by the incoming
 gradient.  Gradients with respect to the probe, positions or measurements are
 not provided.
+
+``amplitude_loss_potential(ctx, V, sigma, probe, pos, meas)`` is the same cost
+of a real potential V with slices t = exp(i sigma V) (Section II-B: V is the
+scattering potential); the transmission and the chain rule
+dF/dV = sigma Im(conj(t) dF/dt) run in the library's elementwise kernels.
 """
 from __future__ import annotations
 
@@ -41,3 +46,31 @@ def amplitude_loss(lib_ctx: B.Context, obj: torch.Tensor, probe: torch.Tensor, p
                    meas: torch.Tensor) -> torch.Tensor:
     """F(V) = sum_i sum_q (|G(p_i, V)| - sqrt(meas_i))^2 with a fused-kernel adjoint for autograd."""
     return _AmplitudeLoss.apply(obj, probe, pos, meas, lib_ctx)
+
+
+class _AmplitudeLossPotential(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, V, sigma, probe, pos, meas, lib_ctx):
+        t = B.ptycho_potential_transmission(lib_ctx, V.detach(), sigma)
+        loss = B.ptycho_loss(lib_ctx, t, probe.detach(), pos, meas.detach())
+        fctx.save_for_backward(t, probe, pos, meas)
+        fctx.sigma, fctx.lib_ctx = float(sigma), lib_ctx
+        return loss.view(())
+
+    @staticmethod
+    def backward(fctx, grad_out):
+        t, probe, pos, meas = fctx.saved_tensors
+        if fctx.needs_input_grad[2] or fctx.needs_input_grad[4]:
+            raise RuntimeError("amplitude_loss_potential differentiates with respect to the potential only")
+        grad = None
+        if fctx.needs_input_grad[0]:
+            scale = grad_out.detach().to(torch.float64).reshape(1).contiguous()
+            _, gt = B.ptycho_loss_grad(fctx.lib_ctx, t, probe.detach(), pos, meas.detach(), grad_scale=scale)
+            grad = B.ptycho_potential_gradient(fctx.lib_ctx, t, gt, fctx.sigma)
+        return grad, None, None, None, None, None
+
+
+def amplitude_loss_potential(lib_ctx: B.Context, V: torch.Tensor, sigma: float, probe: torch.Tensor,
+                             pos: torch.Tensor, meas: torch.Tensor) -> torch.Tensor:
+    """F(exp(i sigma V)) for a float32 [S, H, W] potential V, differentiable with respect to V."""
+    return _AmplitudeLossPotential.apply(V, sigma, probe, pos, meas, lib_ctx)

@@ -400,6 +400,45 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
   return PTYCHO_OK;
 }
 
+namespace {
+int check_plane(const ptycho_ctx* c, int32_t H, int32_t W, int64_t ss, int32_t ld, const void* p, const char* what) {
+  if (!p) return fail(PTYCHO_E_ARG, "null %s", what);
+  if (ld < W || (c->S > 1 && ss < static_cast<int64_t>(H) * ld))
+    return fail(PTYCHO_E_SHAPE, "%s strides do not cover %dx%d", what, H, W);
+  return PTYCHO_OK;
+}
+}  // namespace
+
+int ptycho_potential_transmission(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma, const float* V,
+                                  int64_t v_slice_stride, int32_t v_ld, void* t, int64_t t_slice_stride,
+                                  int32_t t_ld) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (H < 0 || W < 0 || !std::isfinite(sigma)) return fail(PTYCHO_E_ARG, "bad size or sigma");
+  int rc = check_plane(ctx, H, W, v_slice_stride, v_ld, V, "potential");
+  if (rc == PTYCHO_OK) rc = check_plane(ctx, H, W, t_slice_stride, t_ld, t, "transmission");
+  if (rc != PTYCHO_OK) return rc;
+  if (H == 0 || W == 0) return PTYCHO_OK;
+  PT_HIP(ptycho::launch_potential(0, sigma, ctx->S, H, W, V, v_slice_stride, v_ld, static_cast<float2*>(t), nullptr,
+                                  t_slice_stride, t_ld, nullptr, 0, 0, nullptr, 0, 0, ctx->stream));
+  return PTYCHO_OK;
+}
+
+int ptycho_potential_gradient(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma, const void* t,
+                              int64_t t_slice_stride, int32_t t_ld, const void* grad_t, int64_t g_slice_stride,
+                              int32_t g_ld, float* grad_V, int64_t gv_slice_stride, int32_t gv_ld) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (H < 0 || W < 0 || !std::isfinite(sigma)) return fail(PTYCHO_E_ARG, "bad size or sigma");
+  int rc = check_plane(ctx, H, W, t_slice_stride, t_ld, t, "transmission");
+  if (rc == PTYCHO_OK) rc = check_plane(ctx, H, W, g_slice_stride, g_ld, grad_t, "gradient");
+  if (rc == PTYCHO_OK) rc = check_plane(ctx, H, W, gv_slice_stride, gv_ld, grad_V, "potential gradient");
+  if (rc != PTYCHO_OK) return rc;
+  if (H == 0 || W == 0) return PTYCHO_OK;
+  PT_HIP(ptycho::launch_potential(1, sigma, ctx->S, H, W, nullptr, 0, 0, nullptr, static_cast<const float2*>(t),
+                                  t_slice_stride, t_ld, static_cast<const float2*>(grad_t), g_slice_stride, g_ld,
+                                  grad_V, gv_slice_stride, gv_ld, ctx->stream));
+  return PTYCHO_OK;
+}
+
 int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval) {
   if (!ctx) return fail(PTYCHO_E_ARG, "null context");
   if (interval < 1 || interval > 64) return fail(PTYCHO_E_ARG, "checkpoint interval %d outside [1, 64]", interval);

@@ -88,6 +88,9 @@ hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);
+hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const float* V, long long vs, long long vld,
+                            float2* t_out, const float2* t_in, long long ts, long long tld, const float2* g,
+                            long long gs, long long gld, float* gv, long long gvs, long long gvld, hipStream_t st);
 hipError_t launch_box_exchange(const float2* src, long long sslice, long long sld, float2* dst, long long dslice,
                                long long dld, int S, int oh, int ow, bool replace, float alpha, hipStream_t st);
 hipError_t launch_tile_accumulate(const float2* tile, int S, int eh, int ew, float2* grad, long long gslice,

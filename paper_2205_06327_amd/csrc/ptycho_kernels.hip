@@ -709,6 +709,30 @@ __global__ void box_exchange_kernel(const float2* __restrict__ src, long long ss
   }
 }
 
+// Real-potential parametrisation of the slices, t = exp(i sigma V): the
+// transmission from the potential (mode 0) and the chain rule of the complex
+// gradient G = dF/dRe t + i dF/dIm t to the potential, dF/dV = sigma Im(conj(t) G)
+// (mode 1).  Workgroups walk rows of one slice (blockIdx.y), threads columns.
+__global__ void potential_kernel(int mode, float sigma, int H, int W, const float* __restrict__ V, long long vs,
+                                 long long vld, float2* __restrict__ t_out, const float2* __restrict__ t_in,
+                                 long long ts, long long tld, const float2* __restrict__ g, long long gs,
+                                 long long gld, float* __restrict__ gv, long long gvs, long long gvld) {
+  const long long s = blockIdx.y;
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    for (int x = threadIdx.x; x < W; x += blockDim.x) {
+      if (mode == 0) {
+        float sn, cs;
+        sincosf(sigma * V[s * vs + y * vld + x], &sn, &cs);
+        t_out[s * ts + y * tld + x] = make_float2(cs, sn);
+      } else {
+        const float2 t = t_in[s * ts + y * tld + x];
+        const float2 d = g[s * gs + y * gld + x];
+        gv[s * gvs + y * gvld + x] = sigma * (t.x * d.y - t.y * d.x);
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
@@ -800,6 +824,15 @@ hipError_t launch_box_exchange(const float2* src, long long sslice, long long sl
 
 hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st) {
   hipLaunchKernelGGL(copy_ints_kernel, dim3(static_cast<unsigned>((n + 63) / 64)), dim3(64), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const float* V, long long vs, long long vld,
+                            float2* t_out, const float2* t_in, long long ts, long long tld, const float2* g,
+                            long long gs, long long gld, float* gv, long long gvs, long long gvld, hipStream_t st) {
+  const unsigned rows = static_cast<unsigned>(H < 1024 ? H : 1024);
+  hipLaunchKernelGGL(potential_kernel, dim3(rows, static_cast<unsigned>(S)), dim3(256), 0, st, mode, sigma, H, W, V,
+                     vs, vld, t_out, t_in, ts, tld, g, gs, gld, gv, gvs, gvld);
   return hipGetLastError();
 }
 

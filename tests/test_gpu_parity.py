@@ -207,3 +207,33 @@ def test_checkpointed_wave_recomputation(torch_cuda):
     assert results[4][2] < b1 and results[16][2] == b1
     with pytest.raises(pt.PtychoError):
         ctx.set_checkpoint(0)
+
+
+def test_potential_parametrisation_autograd(torch_cuda):
+    """t = exp(i sigma V) and dF/dV = sigma Im(conj(t) dF/dt) in the library's kernels, through
+    torch autograd, against the oracle's chain rule (pinned by central differences)."""
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.autograd import amplitude_loss_potential
+    spec = ps.with_overrides(ps.workload("ms8-1024-m128"), W=256, ny=3, nx=3, step=14, S=3)
+    say("real-potential parametrisation, 3 slices, 9 positions")
+    d = problem(spec)
+    sigma = 0.8
+    V = (np.angle(d["obj_eval"]) / sigma).astype(np.float32)
+    t_ref = oracle.transmission_from_potential(V, sigma)
+    L_ref, _, G_ref = oracle.loss_and_gradient(t_ref, d["probe"], d["pos"], d["meas"], d["H"])
+    gV_ref = oracle.potential_gradient(t_ref, G_ref, sigma)
+    dev = "cuda:0"
+    ctx = context(spec, spec.n)
+    Vd = torch.tensor(V, device=dev, requires_grad=True)
+    t_gpu = pt.ptycho_potential_transmission(ctx, Vd.detach(), sigma)
+    torch.cuda.synchronize()
+    assert np.abs(t_gpu.cpu().numpy() - t_ref).max() <= 1e-6
+    probe = torch.tensor(d["probe"], dtype=torch.complex64, device=dev)
+    pos = torch.tensor(d["pos"], device=dev)
+    meas = torch.tensor(d["meas"], device=dev)
+    loss = amplitude_loss_potential(ctx, Vd, sigma, probe, pos, meas)
+    (3.0 * loss).backward()
+    assert ctx.check() == 0
+    assert abs(float(loss.item()) - L_ref) <= 1e-5 * L_ref
+    assert rel_l2(Vd.grad.cpu().numpy(), 3.0 * gV_ref) <= 1e-4

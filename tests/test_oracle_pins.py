@@ -424,3 +424,28 @@ def test_alg1_tiles_descend(batch, T):
                                   batch=batch, T=T, iterations=4)
     assert all(b < a for a, b in zip(losses, losses[1:]))
     assert oracle.loss_and_gradient(V, d["probe"], d["pos"], meas, H)[0] < losses[0]
+
+
+def test_potential_gradient_by_central_differences():
+    # F(V) = F(exp(i sigma V)) on a tiny 2-slice problem; the chain rule against central
+    # differences on a few voxels of the real potential
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=24, ny=2, nx=2, step=4, S=2, M=16, R=4.0, C=1.0,
+                             strength=0.3)
+    d = ps.build_inputs(spec)
+    H = oracle.fresnel_propagator(spec.M, LAM, DZ, PIX)
+    meas = oracle.forward(d["obj_true"], d["probe"], d["pos"], H)
+    sigma = 0.7
+    rng = np.random.default_rng(5)
+    V = rng.uniform(0.0, 0.5, size=(2, spec.W, spec.W))
+    t = oracle.transmission_from_potential(V, sigma)
+    G = oracle.loss_and_gradient(t, d["probe"], d["pos"], meas, H)[2]
+    gV = oracle.potential_gradient(t, G, sigma)
+    h = 1e-6
+    for s_, y, x in [(0, 9, 9), (1, 12, 7), (0, 5, 14), (1, 17, 17)]:
+        Vp, Vm = V.copy(), V.copy()
+        Vp[s_, y, x] += h
+        Vm[s_, y, x] -= h
+        Fp = oracle.loss_and_gradient(oracle.transmission_from_potential(Vp, sigma), d["probe"], d["pos"], meas, H)[0]
+        Fm = oracle.loss_and_gradient(oracle.transmission_from_potential(Vm, sigma), d["probe"], d["pos"], meas, H)[0]
+        fd = (Fp - Fm) / (2 * h)
+        assert abs(fd - gV[s_, y, x]) <= 1e-6 * max(1.0, abs(fd)) + 1e-7 * np.abs(gV).max()
