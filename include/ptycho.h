@@ -93,7 +93,8 @@ enum {
  * max_positions bounds n of a single loss/gradient call (the context keeps a
  * per-position loss array of that length); 0 picks a default of 4096.
  * The context also owns the incident-wave store of the adjoint sweep:
- * (#CUs) x (S-1) x M*M complex64.
+ * (#CUs) x (S-1) x M*M complex64 (see ptycho_set_checkpoint), and the
+ * probe-gradient partial sums, (#CUs) x M*M complex64.
  * Returns PTYCHO_E_UNSUPPORTED for other M or S, PTYCHO_E_NOMEM if the
  * workspace cannot be allocated.
  */
@@ -179,6 +180,23 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
                      int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
                      double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride,
                      int32_t grad_ld, uint32_t flags, const double* grad_scale);
+
+/*
+ * ptycho_loss_grad_probe: ptycho_loss_grad plus the gradient with respect to
+ * the probe, probe_grad = dF/dRe P + i dF/dIm P = sum_i chi_{0,i} conj(t_0[window_i])
+ * (chi_0 the adjoint wave at the first slice, Eq. 2 applied to psi_0 = P),
+ * complex64 [M][M] on the device, overwritten (added with PTYCHO_ACCUMULATE;
+ * the flag applies to grad, loss and probe_grad alike) and scaled like grad.
+ * Each workgroup sums its positions into a partial buffer owned by the
+ * context; the partial sums are added in workgroup order, so probe_grad does
+ * not depend on timing.  E_ARG if probe_grad aliases grad or the probe;
+ * otherwise the errors of ptycho_loss_grad.  probe_grad = NULL is
+ * ptycho_loss_grad.
+ */
+int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                           double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
+                           void* probe_grad, uint32_t flags, const double* grad_scale);
 
 /*
  * ptycho_loss: the amplitude cost F (Eq. 1) alone -- the forward sweep and

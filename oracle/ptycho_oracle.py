@@ -59,6 +59,7 @@ __all__ = [
     "forward",
     "loss_and_gradient",
     "position_loss_and_patch_gradients",
+    "probe_gradient",
     "tile_bounds",
     "bin_positions",
     "extended_box",
@@ -157,6 +158,32 @@ def position_loss_and_patch_gradients(obj: np.ndarray, probe: np.ndarray, y0: in
             t_s = _window(obj[s], y0, x0, M)
             chi = np.fft.ifft2(np.conj(H) * np.fft.fft2(chi * np.conj(t_s)))
     return loss, grads
+
+
+def probe_gradient(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray,
+                   H: np.ndarray) -> np.ndarray:
+    """dF/dRe P + i dF/dIm P (complex128 [M, M]).
+
+    phi_0 = P * t_0[window] is symmetric in P and t_0, so each position adds
+    chi_0 * conj(t_0[window]), chi_0 being the adjoint wave at the first slice:
+    chi_{S-1} = F^H g, chi_{s-1} = F^-1(conj(H) F(chi_s conj(t_s))) down to s = 1."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    M = probe.shape[0]
+    S = obj.shape[0]
+    out = np.zeros((M, M), dtype=np.complex128)
+    for i, (y0, x0) in enumerate(np.asarray(pos)):
+        y0, x0 = int(y0), int(x0)
+        _, far = exit_waves(obj, probe, y0, x0, H)
+        a = np.sqrt(np.asarray(meas[i], dtype=np.float64))
+        mod = np.abs(far)
+        u = np.zeros_like(far)
+        nz = mod > 0
+        u[nz] = far[nz] / mod[nz]
+        chi = (M * M) * np.fft.ifft2(2.0 * (mod - a) * u)
+        for s in range(S - 1, 0, -1):
+            chi = np.fft.ifft2(np.conj(H) * np.fft.fft2(chi * np.conj(_window(obj[s], y0, x0, M))))
+        out += chi * np.conj(_window(obj[0], y0, x0, M))
+    return out
 
 
 def loss_and_gradient(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray,

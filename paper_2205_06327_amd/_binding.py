@@ -38,7 +38,7 @@ EXPORTED = (
     "ptycho_batch_loss_grad", "ptycho_batch_update", "ptycho_batch_step", "ptycho_batch_capture",
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
-    "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient",
+    "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
 )
 
 
@@ -71,6 +71,8 @@ def lib() -> ctypes.CDLL:
             "ptycho_forward": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp]),
             "ptycho_loss_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
                                                 c_vp, c_vp, c_vp, c_i64, c_i32, c_u32, c_vp]),
+            "ptycho_loss_grad_probe": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32,
+                                                      c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_vp, c_u32, c_vp]),
             "ptycho_loss": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
                                            c_vp, c_vp, c_u32]),
             "ptycho_tile_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i64, c_i32, c_i32, c_i32,
@@ -281,10 +283,12 @@ def ptycho_loss(ctx: Context, obj, probe, pos, meas, loss=None, loss_per_pos=Non
 
 
 def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, loss_per_pos=None,
-                     accumulate: bool = False, grad_scale=None):
+                     accumulate: bool = False, grad_scale=None, probe_grad=None):
     """(loss float64 [1], grad complex64 [S, H, W]) of the amplitude cost.
 
     grad_scale: optional float64 [1] device tensor multiplying the gradient.
+    probe_grad: optional complex64 [M, M] device tensor that receives dF/dP
+    (ptycho_loss_grad_probe).
     """
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
@@ -311,10 +315,17 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
         _need(grad_scale, torch.float64, (1,), "grad_scale")
         gs = c_vp(grad_scale.data_ptr())
     ctx._bind_stream()
-    _check(lib().ptycho_loss_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
-                                  c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
-                                  c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
-                                  PTYCHO_ACCUMULATE if accumulate else 0, gs))
+    flags = PTYCHO_ACCUMULATE if accumulate else 0
+    if probe_grad is None:
+        _check(lib().ptycho_loss_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                      c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
+                                      c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1), flags, gs))
+    else:
+        _need(probe_grad, torch.complex64, (M, M), "probe_grad")
+        _check(lib().ptycho_loss_grad_probe(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                            c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()),
+                                            lpp, c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
+                                            c_vp(probe_grad.data_ptr()), flags, gs))
     return loss, grad
 
 

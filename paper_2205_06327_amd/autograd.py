@@ -6,8 +6,9 @@ nothing but the inputs; its backward calls the fused loss+gradient kernel,
 which runs the multislice forward again for every position, keeps the
 incident waves of that position only for the duration of its own adjoint
 sweep, and scatter-adds dF/dRe t + i dF/dIm t (Eq. 2) scaled by the incoming
-gradient.  Gradients with respect to the probe, positions or measurements are
-not provided.
+gradient; when the probe requires a gradient the same launch also sums
+dF/dP = sum_i chi_0 conj(t_0[window]).  Gradients with respect to positions or
+measurements are not provided.
 
 ``amplitude_loss_potential(ctx, V, sigma, probe, pos, meas)`` is the same cost
 of a real potential V with slices t = exp(i sigma V) (Section II-B: V is the
@@ -32,14 +33,18 @@ class _AmplitudeLoss(torch.autograd.Function):
     @staticmethod
     def backward(fctx, grad_out):
         obj, probe, pos, meas = fctx.saved_tensors
-        if fctx.needs_input_grad[1] or fctx.needs_input_grad[3]:
-            raise RuntimeError("amplitude_loss differentiates with respect to the object only")
-        grad = None
-        if fctx.needs_input_grad[0]:
+        if fctx.needs_input_grad[3]:
+            raise RuntimeError("amplitude_loss differentiates with respect to the object and the probe only")
+        grad = pgrad = None
+        if fctx.needs_input_grad[0] or fctx.needs_input_grad[1]:
             scale = grad_out.detach().to(torch.float64).reshape(1).contiguous()
+            if fctx.needs_input_grad[1]:
+                pgrad = torch.empty_like(probe)
             _, grad = B.ptycho_loss_grad(fctx.lib_ctx, obj.detach(), probe.detach(), pos, meas.detach(),
-                                         grad_scale=scale)
-        return grad, None, None, None, None
+                                         grad_scale=scale, probe_grad=pgrad)
+            if not fctx.needs_input_grad[0]:
+                grad = None
+        return grad, pgrad, None, None, None
 
 
 def amplitude_loss(lib_ctx: B.Context, obj: torch.Tensor, probe: torch.Tensor, pos: torch.Tensor,

@@ -57,6 +57,7 @@ struct ptycho_ctx {
   int capacity = 0;        // positions per call
   float2* d_tw = nullptr;  // W_M^e
   float2* d_h = nullptr;   // separable propagator factor
+  float2* d_probe_part = nullptr;  // probe-gradient partial sums, grid * M*M
   float2* d_ws = nullptr;  // incident-wave store, grid * ws_slots(S, ck) * M*M
   int ck = 1;              // checkpoint interval of the incident waves
   double* d_loss = nullptr;  // per-position losses [capacity]
@@ -78,6 +79,7 @@ void free_ctx(ptycho_ctx* c) {
   if (c->d_tw) (void)hipFree(c->d_tw);
   if (c->d_h) (void)hipFree(c->d_h);
   if (c->d_ws) (void)hipFree(c->d_ws);
+  if (c->d_probe_part) (void)hipFree(c->d_probe_part);
   if (c->d_loss) (void)hipFree(c->d_loss);
   if (c->d_status) (void)hipFree(c->d_status);
   delete c;
@@ -133,12 +135,18 @@ int launch_fused_timed(ptycho_ctx* c, const ptycho::KernelArgs& a, int mode) {
   return PTYCHO_OK;
 }
 
-int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, double* loss, uint32_t flags) {
+int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, double* loss, uint32_t flags,
+                  float2* probe_grad = nullptr) {
   const bool acc = (flags & PTYCHO_ACCUMULATE) != 0;
   if (!acc) PT_HIP(ptycho::launch_zero_slices(a.grad, c->S, gh, gw, a.gslice, a.gld, c->stream));
   if (a.n > 0) {
-    int rc = launch_fused_timed(c, a, ptycho::kModeLossGrad);
+    a.probe_part = c->d_probe_part;
+    int rc = launch_fused_timed(c, a, probe_grad ? ptycho::kModeLossGradProbe : ptycho::kModeLossGrad);
     if (rc != PTYCHO_OK) return rc;
+  }
+  if (probe_grad) {  // sum the launched workgroups' partial sums (none when n = 0)
+    const int parts = a.n < c->grid ? a.n : c->grid;
+    PT_HIP(ptycho::launch_probe_reduce(c->d_probe_part, parts, c->M, probe_grad, acc, c->stream));
   }
   PT_HIP(ptycho::launch_finalize_loss(c->d_loss, a.n, loss, acc, c->stream));
   return PTYCHO_OK;
@@ -191,12 +199,13 @@ int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, d
       (e = hipMalloc(&c->d_h, M * sizeof(float2))) != hipSuccess ||
       (e = hipMalloc(&c->d_loss, static_cast<size_t>(c->capacity) * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->d_status, sizeof(unsigned))) != hipSuccess ||
-      (ws_elems > 0 && (e = hipMalloc(&c->d_ws, ws_elems * sizeof(float2))) != hipSuccess)) {
+      (ws_elems > 0 && (e = hipMalloc(&c->d_ws, ws_elems * sizeof(float2))) != hipSuccess) ||
+      (e = hipMalloc(&c->d_probe_part, static_cast<size_t>(c->grid) * M * M * sizeof(float2))) != hipSuccess) {
     free_ctx(c);
     return fail(PTYCHO_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   c->bytes = static_cast<int64_t>(2 * M * sizeof(float2) + c->capacity * sizeof(double) + sizeof(unsigned) +
-                                  ws_elems * sizeof(float2));
+                                  ws_elems * sizeof(float2) + static_cast<size_t>(c->grid) * M * M * sizeof(float2));
   if ((e = hipMemcpy(c->d_tw, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(c->d_h, h.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_status, 0, sizeof(unsigned))) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
@@ -260,6 +269,14 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
                      double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld, uint32_t flags,
                      const double* grad_scale) {
+  return ptycho_loss_grad_probe(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas, loss, loss_per_pos, grad,
+                                grad_slice_stride, grad_ld, nullptr, flags, grad_scale);
+}
+
+int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                           double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
+                           void* probe_grad, uint32_t flags, const double* grad_scale) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
   if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
@@ -287,7 +304,9 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
   a.gslice = grad_slice_stride;
   a.gld = grad_ld;
   a.grad_scale = grad_scale;
-  return run_loss_grad(ctx, a, H, W, loss, flags);
+  if (probe_grad && (probe_grad == grad || probe_grad == probe))
+    return fail(PTYCHO_E_ARG, "probe gradient aliases the gradient or the probe");
+  return run_loss_grad(ctx, a, H, W, loss, flags, static_cast<float2*>(probe_grad));
 }
 
 int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,

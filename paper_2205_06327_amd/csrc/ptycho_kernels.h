@@ -9,6 +9,7 @@ namespace ptycho {
 constexpr int kModeIntensity = 0;  // |Psi|^2
 constexpr int kModeLoss = 1;       // f_i only
 constexpr int kModeLossGrad = 2;   // f_i and the adjoint gradient
+constexpr int kModeLossGradProbe = 3;  // f_i, the object gradient and the probe gradient
 
 // Wave-store slots (M*M complex each) per workgroup for S slices with the
 // incident waves checkpointed every ck slices: the checkpoints psi_ck,
@@ -44,6 +45,7 @@ struct KernelArgs {
   int ck;                // checkpoint interval of the incident waves
   unsigned* status;
   const double* grad_scale;  // nullable device scalar multiplying the gradient
+  float2* probe_part;    // probe-gradient mode: per-workgroup partial sums, grid * M*M (layout-A order)
 };
 
 // One reconstruction of a batch (device copy of the public descriptor plus
@@ -88,6 +90,8 @@ hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);
+hipError_t launch_probe_reduce(const float2* part, int parts, int M, float2* probe_grad, bool accumulate,
+                               hipStream_t st);
 hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const float* V, long long vs, long long vld,
                             float2* t_out, const float2* t_in, long long ts, long long tld, const float2* g,
                             long long gs, long long gld, float* gv, long long gvs, long long gvld, hipStream_t st);

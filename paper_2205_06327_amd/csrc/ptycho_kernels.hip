@@ -290,6 +290,7 @@ struct PositionJob {
   long long gld, gslice;
   float gscale;          // 2 x the upstream gradient factor
   int ck;                // checkpoint interval of the incident waves (1: all kept)
+  float2* probe_part;    // probe-gradient mode: this workgroup's partial sum (layout A)
 };
 
 // Per-workgroup state shared by all positions a workgroup processes.
@@ -324,7 +325,7 @@ __device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* _
 template <class G, int MODE, bool LINES = false, bool CKPT = false>
 __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
                                                float2 hy, float2* __restrict__ ws, const Lanes<G>& L) {
-  constexpr bool GRAD = MODE == kModeLossGrad;
+  constexpr bool GRAD = MODE == kModeLossGrad || MODE == kModeLossGradProbe;
   constexpr bool LOSS = MODE != kModeIntensity;
   const int S = jb.S;
   // Incident waves for the adjoint sweep.  The slices are cut into segments of
@@ -415,6 +416,20 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
     // atomics then drain while the next propagation runs on LDS and VALU.
     float2 g[G::R];
     if (s == 0) {
+      if constexpr (MODE == kModeLossGradProbe) {
+        // dF/dP += chi_0 conj(t_0[window]) into this workgroup's partial sum (only this
+        // thread touches these elements, so a plain read-modify-write is race-free)
+        load_window<G>(g, jb.win, jb.ld, L);
+        float2* __restrict__ pp = jb.probe_part + opaque_zero();
+        float2 acc[G::R];
+        sfor<G::R>([&](auto rc) { acc[decltype(rc)::value] = pp[decltype(rc)::value * G::T + L.tid]; });
+        __builtin_amdgcn_sched_barrier(0);
+        sfor<G::R>([&](auto rc) {
+          constexpr int r = decltype(rc)::value;
+          pp[r * G::T + L.tid] = cadd(acc[r], cmulc(v[r], g[r]));
+        });
+        __builtin_amdgcn_sched_barrier(0);
+      }
       load_window<G>(g, jb.probe, G::M, L);
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
@@ -495,6 +510,11 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
   jb.gslice = a.gslice;
   jb.gscale = 2.0f * (a.grad_scale != nullptr ? static_cast<float>(*a.grad_scale) : 1.0f);
   jb.ck = a.ck;
+  jb.probe_part = nullptr;
+  if constexpr (MODE == kModeLossGradProbe) {
+    jb.probe_part = a.probe_part + static_cast<long long>(blockIdx.x) * (G::M * G::M);
+    sfor<G::R>([&](auto rc) { jb.probe_part[decltype(rc)::value * G::T + L.tid] = make_float2(0.f, 0.f); });
+  }
 
   for (int j = 0;; ++j) {
     const int p = job_position(j, a.n, static_cast<int>(gridDim.x));
@@ -733,6 +753,27 @@ __global__ void potential_kernel(int mode, float sigma, int H, int W, const floa
   }
 }
 
+// probe_grad[y][x] (+)= sum over the workgroups' partial sums, which hold pixel
+// (y, x) = (Y2*r + n2, x) at index r*T + n2*M + x (layout A).  The sum runs in
+// workgroup order, so the result does not depend on timing.
+template <int M>
+__global__ void probe_reduce_kernel(const float2* __restrict__ part, int parts, float2* __restrict__ out,
+                                    int accumulate) {
+  using G = Geo<M>;
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= M * M) return;
+  const int r = i / G::T, tid = i % G::T;
+  const int y = G::Y2 * r + tid / M, x = tid % M;
+  float sx = 0.f, sy = 0.f;
+  for (int b = 0; b < parts; ++b) {
+    const float2 v = part[static_cast<long long>(b) * (M * M) + i];
+    sx += v.x;
+    sy += v.y;
+  }
+  float2& o = out[y * M + x];
+  o = accumulate ? make_float2(o.x + sx, o.y + sy) : make_float2(sx, sy);
+}
+
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
@@ -748,6 +789,7 @@ static hipError_t launch_fused_m(const KernelArgs& a, int mode, int grid, hipStr
     case kModeIntensity: return launch_fused_t<M, kModeIntensity>(a, grid, st);
     case kModeLoss: return launch_fused_t<M, kModeLoss>(a, grid, st);
     case kModeLossGrad: return launch_fused_t<M, kModeLossGrad>(a, grid, st);
+    case kModeLossGradProbe: return launch_fused_t<M, kModeLossGradProbe>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -833,6 +875,21 @@ hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const fl
   const unsigned rows = static_cast<unsigned>(H < 1024 ? H : 1024);
   hipLaunchKernelGGL(potential_kernel, dim3(rows, static_cast<unsigned>(S)), dim3(256), 0, st, mode, sigma, H, W, V,
                      vs, vld, t_out, t_in, ts, tld, g, gs, gld, gv, gvs, gvld);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_reduce(const float2* part, int parts, int M, float2* probe_grad, bool accumulate,
+                               hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((M * M + 255) / 256);
+  if (M == 128) {
+    hipLaunchKernelGGL(probe_reduce_kernel<128>, dim3(blocks), dim3(256), 0, st, part, parts, probe_grad,
+                       accumulate ? 1 : 0);
+  } else if (M == 64) {
+    hipLaunchKernelGGL(probe_reduce_kernel<64>, dim3(blocks), dim3(256), 0, st, part, parts, probe_grad,
+                       accumulate ? 1 : 0);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

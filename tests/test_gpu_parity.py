@@ -237,3 +237,36 @@ def test_potential_parametrisation_autograd(torch_cuda):
     assert ctx.check() == 0
     assert abs(float(loss.item()) - L_ref) <= 1e-5 * L_ref
     assert rel_l2(Vd.grad.cpu().numpy(), 3.0 * gV_ref) <= 1e-4
+
+
+def test_probe_gradient(torch_cuda):
+    """dF/dP from the same launch as the object gradient, through autograd and with
+    accumulation, against the oracle (pinned by torch complex autograd on tiny grids)."""
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.autograd import amplitude_loss
+    for name, spec in [("m128 S=4", ps.with_overrides(ps.workload("ms8-1024-m128"), W=256, ny=3, nx=4, step=14, S=4)),
+                       ("m64 S=3", ps.with_overrides(ps.workload("2d-256-m64"), W=160, ny=5, nx=5, step=7, S=3,
+                                                     noise=True, strength=0.05))]:
+        say(f"probe gradient, {name}, {spec.n} positions")
+        d = problem(spec)
+        GP = oracle.probe_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])
+        G = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+        t = to_dev(d)
+        ctx = context(spec, spec.n)
+        obj = t["obj"].clone().requires_grad_(True)
+        probe = t["probe"].clone().requires_grad_(True)
+        loss = amplitude_loss(ctx, obj, probe, t["pos"], t["meas"])
+        (0.5 * loss).backward()
+        assert ctx.check() == 0
+        assert rel_l2(probe.grad.cpu().numpy(), 0.5 * GP) <= 1e-4
+        assert rel_l2(obj.grad.cpu().numpy(), 0.5 * G) <= 1e-4
+        # accumulate: a second call adds the same again
+        pg = torch.zeros_like(t["probe"])
+        g = torch.zeros_like(t["obj"])
+        loss_d = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        for _ in range(2):
+            pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], grad=g, loss=loss_d,
+                                accumulate=True, probe_grad=pg)
+        torch.cuda.synchronize()
+        assert rel_l2(pg.cpu().numpy(), 2 * GP) <= 1e-4

@@ -243,7 +243,7 @@ def test_torch_autograd_cross_check():
     meas = _meas_for(obj, probe, pos, H, rng)
     _, _, G = oracle.loss_and_gradient(obj, probe, pos, meas, H)
     t = torch.tensor(obj, dtype=torch.complex128, requires_grad=True)
-    P = torch.tensor(probe, dtype=torch.complex128)
+    P = torch.tensor(probe, dtype=torch.complex128, requires_grad=True)
     Ht = torch.tensor(H, dtype=torch.complex128)
     loss = 0.0
     for i, (y0, x0) in enumerate(pos):
@@ -256,6 +256,8 @@ def test_torch_autograd_cross_check():
         loss = loss + torch.sum((amp - torch.sqrt(torch.tensor(meas[i]))) ** 2)
     loss.backward()
     np.testing.assert_allclose(t.grad.numpy(), G, rtol=0, atol=1e-12 * np.abs(G).max())
+    GP = oracle.probe_gradient(obj, probe, pos, meas, H)
+    np.testing.assert_allclose(P.grad.numpy(), GP, rtol=0, atol=1e-12 * np.abs(GP).max())
 
 
 def test_zero_gradient_at_truth_and_locality():
