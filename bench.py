@@ -448,6 +448,14 @@ def main():
         "hbm_roofline_frac_of_step": round(value / hbm_roofline_pos, 4),
         "roofline": roofline,
         "loss": loss_total,
+        # context only: the paper's time-to-solution on its own workload and machine
+        "paper_context": {
+            "reported": "2.2 min for 100 iterations over 16632 positions on 4158 V100 GPUs (Summit)",
+            "position_iterations_per_s": round(16632 * 100 / 132.0, 1),
+            "their_workload": "1024^2 windows, 100 slices, 3072^2 object",
+            "transform_work_per_position_vs_this_workload": round(
+                (4 * 100 - 2) * (1024 ** 2) * 20 / ((4 * S - 2) * (M * M) * math.log2(M * M)), 1),
+        },
     }
 
     if not args.no_checks:
