@@ -7,12 +7,15 @@
 //   chi_{S-1} = DFT^H(2 (|Psi| - a) Psi / |Psi|), grad_s += chi_s conj(psi_s),
 //   chi_{s-1} = IDFT(conj(H) DFT(chi_s conj(t_s))).
 // The wave of a position stays in registers of one workgroup for the whole
-// slice loop; LDS is used only for the two transposing exchanges of every
-// 2D DFT (see fft_lds.hpp).  The incident waves psi_s of the forward sweep
-// are kept in a per-workgroup workspace in HBM and re-read in reverse order by
-// the adjoint sweep.  Gradient patches are added to the caller's gradient with
-// hardware float atomics, laid out so that every atomic instruction covers 32
-// contiguous complex values.
+// slice loop; LDS holds the two transposing exchanges of every 2D DFT (see
+// fft_lds.hpp) and, between propagations, the gradient window being added.
+// The incident waves psi_s of the forward sweep are kept in a per-workgroup
+// workspace in HBM (all of them, or checkpoints from which the adjoint sweep
+// recomputes the rest) and re-read in reverse order by the adjoint sweep.
+// Gradient windows are added to the caller's gradient with hardware float
+// atomics, each instruction covering whole 128-byte lines (128-windows) or 32
+// contiguous complex values (64-windows and the batched launch).  Optional
+// outputs: the probe gradient (per-workgroup partial sums).
 #include "fft_lds.hpp"
 #include "ptycho_kernels.h"
 
