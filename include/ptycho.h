@@ -134,6 +134,19 @@ int ptycho_potential_gradient(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma
                               int32_t g_ld, float* grad_V, int64_t gv_slice_stride, int32_t gv_ld);
 
 /*
+ * ptycho_copy_box: copies an h x w box of S complex64 slices between two
+ * arrays, either of which may be host memory (pinned for asynchronous
+ * transfers) or device memory: element (s, y, x) from
+ * src[s*src_slice_stride + y*src_ld + x] to dst[s*dst_slice_stride + y*dst_ld + x].
+ * One pitched copy per slice on the context stream (hipMemcpy2DAsync); the
+ * streaming tile walk moves extended tiles of a host-resident object and
+ * gradient with it.  E_ARG on null pointers, E_SHAPE on negative sizes or
+ * strides that do not cover the box.
+ */
+int ptycho_copy_box(ptycho_ctx* ctx, int32_t S, int32_t h, int32_t w, const void* src, int64_t src_slice_stride,
+                    int32_t src_ld, void* dst, int64_t dst_slice_stride, int32_t dst_ld);
+
+/*
  * ptycho_set_checkpoint: how the gradient call obtains the incident waves
  * psi_s of its adjoint sweep (Eq. 2 needs psi_s at slice s, in reverse order).
  * The call always recomputes them from the probe and the object (nothing is

@@ -39,6 +39,7 @@ EXPORTED = (
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
+    "ptycho_copy_box",
 )
 
 
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_copy_box": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32]),
             "ptycho_potential_transmission": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
                                                              c_vp, c_i64, c_i32]),
             "ptycho_potential_gradient": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
@@ -454,6 +456,21 @@ def ptycho_potential_gradient(ctx: Context, t, grad_t, sigma: float, grad_V=None
                                            grad_t.stride(1), c_vp(grad_V.data_ptr()), grad_V.stride(0),
                                            grad_V.stride(1)))
     return grad_V
+
+
+def ptycho_copy_box(ctx: Context, src, dst) -> None:
+    """dst[...] = src[...] for complex64 [S, h, w] views (host or device, unit stride along w), one
+    pitched copy per slice on the context stream; pinned host memory makes it asynchronous."""
+    torch = _torch()
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex64 or t.dim() != 3 or t.stride(2) != 1:
+            raise ValueError(f"{name} must be complex64 [S, h, w] with unit stride along w")
+    if tuple(src.shape) != tuple(dst.shape):
+        raise ValueError("src and dst must have one shape")
+    S, h, w = src.shape
+    ctx._bind_stream()
+    _check(lib().ptycho_copy_box(ctx.handle, S, h, w, c_vp(src.data_ptr()), src.stride(0), src.stride(1),
+                                 c_vp(dst.data_ptr()), dst.stride(0), dst.stride(1)))
 
 
 def ptycho_zero_gradient(ctx: Context, grad) -> None:

@@ -458,6 +458,26 @@ int ptycho_potential_gradient(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma
   return PTYCHO_OK;
 }
 
+int ptycho_copy_box(ptycho_ctx* ctx, int32_t S, int32_t h, int32_t w, const void* src, int64_t src_slice_stride,
+                    int32_t src_ld, void* dst, int64_t dst_slice_stride, int32_t dst_ld) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (!src || !dst) return fail(PTYCHO_E_ARG, "null buffer");
+  if (S < 0 || h < 0 || w < 0) return fail(PTYCHO_E_SHAPE, "negative box size");
+  if (src_ld < w || dst_ld < w ||
+      (S > 1 && (src_slice_stride < static_cast<int64_t>(h) * src_ld ||
+                 dst_slice_stride < static_cast<int64_t>(h) * dst_ld)))
+    return fail(PTYCHO_E_SHAPE, "strides do not cover the box");
+  if (S == 0 || h == 0 || w == 0) return PTYCHO_OK;
+  const size_t e = sizeof(float2);
+  for (int32_t s = 0; s < S; ++s) {
+    const char* sp = static_cast<const char*>(src) + static_cast<size_t>(s) * src_slice_stride * e;
+    char* dp = static_cast<char*>(dst) + static_cast<size_t>(s) * dst_slice_stride * e;
+    PT_HIP(hipMemcpy2DAsync(dp, static_cast<size_t>(dst_ld) * e, sp, static_cast<size_t>(src_ld) * e,
+                            static_cast<size_t>(w) * e, static_cast<size_t>(h), hipMemcpyDefault, ctx->stream));
+  }
+  return PTYCHO_OK;
+}
+
 int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval) {
   if (!ctx) return fail(PTYCHO_E_ARG, "null context");
   if (interval < 1 || interval > 64) return fail(PTYCHO_E_ARG, "checkpoint interval %d outside [1, 64]", interval);

@@ -170,54 +170,93 @@ class ResidentTileWalk:
 class StreamingTileWalk:
     """Decomposed gradient with object, measurements and the global gradient in pinned host memory.
 
-    The device holds one extended object box, one tile of measurements and
-    positions, one tile gradient and one gradient box at a time.  For every
-    tile the global gradient's box is brought to the device, the tile gradient
-    is added to it by the library's stitch kernel and the box is written back,
-    so every addition happens on the GPU and the host only moves data.
+    The device holds, per lane, one extended object box, one tile of
+    measurements and positions, one tile gradient and one gradient box.  For
+    every tile the extended object box and the tile's measurements are copied
+    in (pitched copies, ptycho_copy_box), the tile gradient is computed, the
+    global gradient's box is brought in, the tile gradient is added by the
+    library's stitch kernel and the box is written back, so every addition
+    happens on the GPU and the host only moves data.  Tiles alternate between
+    two lanes (context + stream + buffers), so one tile's transfers overlap the
+    other lane's kernel; the gradient boxes of consecutive tiles overlap in the
+    halos, so each tile's read of the global gradient waits for the previous
+    tile's write-back.
     """
 
-    def __init__(self, plan: TileWalk, ctx: B.Context, device="cuda:0"):
+    def __init__(self, plan: TileWalk, ctx: B.Context, device="cuda:0", lanes: int = 2):
         import torch
         self.plan, self.ctx = plan, ctx
         S, M = ctx.S, ctx.M
         eh, ew = plan.max_box
-        ctx.reserve(max(plan.max_count, 1))
-        self.dev = {
-            "obj": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
-            "meas": torch.empty((max(plan.max_count, 1), M, M), dtype=torch.float32, device=device),
-            "pos": torch.empty((max(plan.max_count, 1), 2), dtype=torch.int32, device=device),
-            "tile": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
-            "gbox": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
-            "loss": torch.zeros(len(plan.plans), dtype=torch.float64, device=device),
-        }
+        lanes = max(1, int(lanes))
+        cap = max(plan.max_count, 1)
+        self.ctxs = [ctx] + [B.Context(ctx.M, ctx.S, *ctx.physics, max_positions=cap) for _ in range(lanes - 1)]
+        for c in self.ctxs:
+            c.reserve(cap)
+            if c.checkpoint != ctx.checkpoint:
+                c.set_checkpoint(ctx.checkpoint)
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(lanes)]
+        self.dev = []
+        for _ in range(lanes):
+            self.dev.append({
+                "obj": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
+                "meas": torch.empty((cap, M, M), dtype=torch.float32, device=device),
+                "pos": torch.empty((cap, 2), dtype=torch.int32, device=device),
+                "tile": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
+                "gbox": torch.empty((S, eh, ew), dtype=torch.complex64, device=device),
+            })
+        self.loss = torch.zeros(len(plan.plans), dtype=torch.float64, device=device)
         self.pos_host = torch.tensor(plan.pos_sorted, dtype=torch.int32).pin_memory()
 
     def device_bytes(self) -> int:
-        return sum(t.numel() * t.element_size() for t in self.dev.values())
+        return sum(t.numel() * t.element_size() for d in self.dev for t in d.values()) + \
+            self.loss.numel() * self.loss.element_size()
+
+    def check(self) -> int:
+        st = 0
+        for c in self.ctxs:
+            st |= c.check()
+        return st
 
     def step(self, obj_host, probe, meas_host_sorted, grad_host):
         """grad_host <- decomposed gradient (obj_host [S,H,W] complex64, meas_host [n,M,M] float32, pinned)."""
+        import torch
         S = self.ctx.S
-        d = self.dev
+        for s in self.streams:  # the previous step's write-backs into grad_host have landed
+            s.synchronize()
         grad_host.zero_()
+        cur = torch.cuda.current_stream()
+        start = torch.cuda.Event()
+        start.record(cur)
+        for s in self.streams:
+            s.wait_event(start)
+        written = None  # event after the previous tile's write-back of the global gradient
         for k, p in enumerate(self.plan.plans):
             if p.hi == p.lo:
                 continue
+            lane = k % len(self.ctxs)
+            c, d, s = self.ctxs[lane], self.dev[lane], self.streams[lane]
             ey0, ex0, eh, ew = p.box
             n_k = p.hi - p.lo
             ob = d["obj"].view(-1)[: S * eh * ew].view(S, eh, ew)
             tg = d["tile"].view(-1)[: S * eh * ew].view(S, eh, ew)
             gb = d["gbox"].view(-1)[: S * eh * ew].view(S, eh, ew)
-            ob.copy_(obj_host[:, ey0:ey0 + eh, ex0:ex0 + ew], non_blocking=True)
-            d["meas"][:n_k].copy_(meas_host_sorted[p.lo:p.hi], non_blocking=True)
-            d["pos"][:n_k].copy_(self.pos_host[p.lo:p.hi], non_blocking=True)
-            B.ptycho_tile_grad(self.ctx, ob, p.box, p.tile, self.plan.halo, self.plan.H, self.plan.W, probe,
-                               d["pos"][:n_k], d["meas"][:n_k], tile_grad=tg, loss=d["loss"][k:k + 1])
-            gb.copy_(grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew], non_blocking=True)
-            B.ptycho_tile_accumulate(self.ctx, tg, (0, 0, eh, ew), gb)
-            grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew].copy_(gb)
-        return d["loss"]
+            with torch.cuda.stream(s):
+                B.ptycho_copy_box(c, obj_host[:, ey0:ey0 + eh, ex0:ex0 + ew], ob)
+                d["meas"][:n_k].copy_(meas_host_sorted[p.lo:p.hi], non_blocking=True)
+                d["pos"][:n_k].copy_(self.pos_host[p.lo:p.hi], non_blocking=True)
+                B.ptycho_tile_grad(c, ob, p.box, p.tile, self.plan.halo, self.plan.H, self.plan.W, probe,
+                                   d["pos"][:n_k], d["meas"][:n_k], tile_grad=tg, loss=self.loss[k:k + 1])
+                if written is not None:
+                    s.wait_event(written)
+                B.ptycho_copy_box(c, grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew], gb)
+                B.ptycho_tile_accumulate(c, tg, (0, 0, eh, ew), gb)
+                B.ptycho_copy_box(c, gb, grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew])
+                written = torch.cuda.Event()
+                written.record(s)
+        for s in self.streams:
+            cur.wait_stream(s)
+        return self.loss
 
 
 def directional_passes(ctx: B.Context, plan: TileWalk, bufs) -> None:
