@@ -313,6 +313,8 @@ def main():
     ap.add_argument("--plain-positions", type=int, default=1024)
     ap.add_argument("--cpu-sample", type=int, default=3072)
     ap.add_argument("--lanes", type=int, default=2, help="streams the resident tile walk alternates between")
+    ap.add_argument("--walk", choices=("all", "lanes"), default="all",
+                    help="all: every tile's gradient in one launch; lanes: one launch per tile on alternating streams")
     ap.add_argument("--checkpoint", type=int, default=1,
                     help="keep every k-th incident wave, recompute the others in the adjoint sweep")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -341,7 +343,8 @@ def main():
 
     import paper_2205_06327_amd as pt
     import ptycho_synth as ps
-    from paper_2205_06327_amd.tilewalk import DecomposedTileWalk, ResidentTileWalk, StreamingTileWalk, TileWalk
+    from paper_2205_06327_amd.tilewalk import (AllTilesWalk, DecomposedTileWalk, ResidentTileWalk,
+                                               StreamingTileWalk, TileWalk)
 
     dev = torch.device("cuda:0")
     cores_avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
@@ -378,7 +381,10 @@ def main():
     del I_true, obj_true
     obj = torch.tensor(inputs["obj_eval"], dtype=torch.complex64, device=dev)
     grad = torch.empty((S, W, W), dtype=torch.complex64, device=dev)
-    walk = ResidentTileWalk(ctx, plan, device=dev, lanes=args.lanes)
+    if args.walk == "all":
+        walk = AllTilesWalk(ctx, plan, device=dev)
+    else:
+        walk = ResidentTileWalk(ctx, plan, device=dev, lanes=args.lanes)
     walk.check()
     torch.cuda.synchronize()
 
@@ -443,7 +449,8 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": spec.name, "positions": spec.n, "slices": S, "object": [W, W], "window": M,
                    "tiles": list(spec.tiles), "halo": spec.halo, "step_px": spec.step, "dose": spec.dose,
-                   "wave_checkpoint_interval": args.checkpoint},
+                   "wave_checkpoint_interval": args.checkpoint,
+                   "walk": "all tiles in one launch" if args.walk == "all" else f"{args.lanes} lanes"},
         "hbm_roofline_positions_per_s": round(hbm_roofline_pos, 1),
         "hbm_roofline_frac_of_step": round(value / hbm_roofline_pos, 4),
         "roofline": roofline,
@@ -468,8 +475,10 @@ def main():
             "rel_l2_decomposed_vs_undecomposed": diff,
             "loss_rel_diff": abs(float(loss_full.item()) - loss_total) / abs(loss_total),
             "undecomposed_gradient_bytes": gfull.numel() * 8,
-            "tile_gradient_bytes": int(walk.tile_bufs[0].numel() * 8),
-            "tile_walk_lanes": walk.lanes,
+            "tile_gradient_bytes": int(max(p.box[2] * p.box[3] for p in plan.plans) * S * 8),
+            "walk": args.walk,
+            "walk_tile_buffers_bytes": int(sum(b.numel() * 8 for b in (walk.bufs if args.walk == "all"
+                                                                       else walk.tile_bufs))),
         }
         # per-tile accumulated-gradient buffers and the directional passes between them
         log("per-tile buffers and directional passes")

@@ -261,6 +261,35 @@ int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int3
                     int32_t* ey1, int32_t* ex0, int32_t* ex1);
 
 /*
+ * ptycho_tiles_grad: the gradients of all tiles of a decomposition in one
+ * persistent launch (Section III): every position adds its window's gradient
+ * into the gradient buffer of the tile that owns it, on that tile's extended
+ * box, exactly as ptycho_tile_grad does tile by tile -- the per-device work of
+ * a tile mesh, run side by side on one GPU.
+ *   tiles:       HOST array of ntiles descriptors (copied into the context,
+ *                at most 4096); tile.grad is a device complex64 [S][eh][ew]
+ *                dense buffer (overwritten unless PTYCHO_ACCUMULATE)
+ *   tile_of_pos: device int32 [n], the owning tile of each position
+ *   pos:         device int32 [n][2], global window corners; obj is the whole
+ *                H x W object.
+ * Host validation as in ptycho_tile_grad for every descriptor (tile inside
+ * the object, box = tile grown by halo and clipped, box >= M, non-null
+ * buffer); on the device a window outside its tile's box raises
+ * PTYCHO_STATUS_HALO, a centre outside its tile or a bad tile index
+ * PTYCHO_STATUS_ASSIGN, and the position is skipped.  *loss is the sum over
+ * all positions (per position in loss_per_pos if non-NULL).
+ */
+typedef struct ptycho_tile_desc {
+  int32_t ty0, ty1, tx0, tx1; /* the tile, global pixels, half-open */
+  int32_t ey0, ex0, eh, ew;   /* its extended box */
+  void* grad;                 /* device complex64 [S][eh][ew] tile gradient (dense) */
+} ptycho_tile_desc;
+int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
+                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                      double* loss_per_pos, uint32_t flags);
+
+/*
  * ptycho_tile_accumulate: the stitch step of the decomposition (Section III,
  * and the final stitch of Alg. 1): adds a tile gradient [S][eh][ew] (dense)
  * into the global gradient at its extended box (ey0, ex0):

@@ -13,6 +13,7 @@ from ._binding import (  # noqa: F401
     ptycho_loss_grad,
     ptycho_tile_accumulate,
     ptycho_tile_grad,
+    ptycho_tiles_grad,
     ptycho_zero_gradient,
     ptycho_box_exchange,
     ptycho_box_axpy,

@@ -29,6 +29,13 @@ ERRORS = {
     -8: "PTYCHO_E_NOMEM",
     -9: "PTYCHO_E_CAPACITY",
 }
+class TileDesc(ctypes.Structure):
+    """ptycho_tile_desc: a tile, its extended box and its gradient buffer."""
+    _fields_ = [("ty0", ctypes.c_int32), ("ty1", ctypes.c_int32), ("tx0", ctypes.c_int32), ("tx1", ctypes.c_int32),
+                ("ey0", ctypes.c_int32), ("ex0", ctypes.c_int32), ("eh", ctypes.c_int32), ("ew", ctypes.c_int32),
+                ("grad", ctypes.c_void_p)]
+
+
 EXPORTED = (
     "ptycho_create", "ptycho_destroy", "ptycho_set_stream", "ptycho_reserve", "ptycho_workspace_bytes",
     "ptycho_forward", "ptycho_loss_grad", "ptycho_tile_grad", "ptycho_bin_positions",
@@ -39,7 +46,7 @@ EXPORTED = (
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
-    "ptycho_copy_box",
+    "ptycho_copy_box", "ptycho_tiles_grad",
 )
 
 
@@ -89,6 +96,8 @@ def lib() -> ctypes.CDLL:
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_copy_box": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32]),
+            "ptycho_tiles_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, ctypes.POINTER(TileDesc),
+                                                 c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32]),
             "ptycho_potential_transmission": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
                                                              c_vp, c_i64, c_i32]),
             "ptycho_potential_gradient": (ctypes.c_int, [c_vp, c_i32, c_i32, ctypes.c_float, c_vp, c_i64, c_i32,
@@ -456,6 +465,40 @@ def ptycho_potential_gradient(ctx: Context, t, grad_t, sigma: float, grad_V=None
                                            grad_t.stride(1), c_vp(grad_V.data_ptr()), grad_V.stride(0),
                                            grad_V.stride(1)))
     return grad_V
+
+
+def ptycho_tiles_grad(ctx: Context, obj, tiles, halo: int, tile_of_pos, probe, pos, meas, loss=None,
+                      loss_per_pos=None, accumulate: bool = False):
+    """All tiles' gradients in one launch.  tiles: sequence of (tile (ty0, ty1, tx0, tx1),
+    box (ey0, ex0, eh, ew), grad complex64 [S, eh, ew] contiguous); tile_of_pos int32 [n] and pos
+    int32 [n, 2] (global) on the device.  Returns the total loss (float64 [1])."""
+    torch = _torch()
+    S, H, W, ss, ld = _obj_geometry(obj)
+    if S != ctx.S:
+        raise ValueError(f"object has {S} slices, context {ctx.S}")
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(pos, torch.int32, None, "pos")
+    n = pos.shape[0]
+    _need(tile_of_pos, torch.int32, (n,), "tile_of_pos")
+    _need(meas, torch.float32, (n, M, M), "meas")
+    arr = (TileDesc * len(tiles))()
+    for k, (tile, box, g) in enumerate(tiles):
+        _need(g, torch.complex64, (S, box[2], box[3]), f"tile gradient {k}")
+        arr[k] = TileDesc(tile[0], tile[1], tile[2], tile[3], box[0], box[1], box[2], box[3], g.data_ptr())
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=obj.device)
+    _need(loss, torch.float64, (1,), "loss")
+    lpp = c_vp(0)
+    if loss_per_pos is not None:
+        _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
+        lpp = c_vp(loss_per_pos.data_ptr())
+    ctx._bind_stream()
+    _check(lib().ptycho_tiles_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, arr, len(tiles), int(halo),
+                                   c_vp(tile_of_pos.data_ptr()), c_vp(probe.data_ptr()), c_vp(pos.data_ptr()), n,
+                                   c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
+                                   PTYCHO_ACCUMULATE if accumulate else 0))
+    return loss
 
 
 def ptycho_copy_box(ctx: Context, src, dst) -> None:

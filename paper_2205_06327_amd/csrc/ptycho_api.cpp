@@ -58,6 +58,8 @@ struct ptycho_ctx {
   float2* d_tw = nullptr;  // W_M^e
   float2* d_h = nullptr;   // separable propagator factor
   float2* d_probe_part = nullptr;  // probe-gradient partial sums, grid * M*M
+  ptycho::TileDesc* d_tiles = nullptr;  // tile table of ptycho_tiles_grad (kMaxTiles entries)
+  std::vector<ptycho::TileDesc> h_tiles;
   float2* d_ws = nullptr;  // incident-wave store, grid * ws_slots(S, ck) * M*M
   int ck = 1;              // checkpoint interval of the incident waves
   double* d_loss = nullptr;  // per-position losses [capacity]
@@ -80,6 +82,7 @@ void free_ctx(ptycho_ctx* c) {
   if (c->d_h) (void)hipFree(c->d_h);
   if (c->d_ws) (void)hipFree(c->d_ws);
   if (c->d_probe_part) (void)hipFree(c->d_probe_part);
+  if (c->d_tiles) (void)hipFree(c->d_tiles);
   if (c->d_loss) (void)hipFree(c->d_loss);
   if (c->d_status) (void)hipFree(c->d_status);
   delete c;
@@ -200,7 +203,8 @@ int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, d
       (e = hipMalloc(&c->d_loss, static_cast<size_t>(c->capacity) * sizeof(double))) != hipSuccess ||
       (e = hipMalloc(&c->d_status, sizeof(unsigned))) != hipSuccess ||
       (ws_elems > 0 && (e = hipMalloc(&c->d_ws, ws_elems * sizeof(float2))) != hipSuccess) ||
-      (e = hipMalloc(&c->d_probe_part, static_cast<size_t>(c->grid) * M * M * sizeof(float2))) != hipSuccess) {
+      (e = hipMalloc(&c->d_probe_part, static_cast<size_t>(c->grid) * M * M * sizeof(float2))) != hipSuccess ||
+      (e = hipMalloc(&c->d_tiles, ptycho::kMaxTiles * sizeof(ptycho::TileDesc))) != hipSuccess) {
     free_ctx(c);
     return fail(PTYCHO_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
@@ -402,6 +406,72 @@ int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t 
   a.gslice = static_cast<long long>(eh) * ew;
   a.gld = ew;
   return run_loss_grad(ctx, a, eh, ew, loss, flags);
+}
+
+int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
+                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                      double* loss_per_pos, uint32_t flags) {
+  int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
+  if (rc != PTYCHO_OK) return rc;
+  if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
+  if (!loss || !tiles || (n > 0 && (!meas || !tile_of_pos))) return fail(PTYCHO_E_ARG, "null pointer argument");
+  if (ntiles < 1 || ntiles > ptycho::kMaxTiles) return fail(PTYCHO_E_ARG, "tile count %d outside [1, %d]", ntiles,
+                                                            ptycho::kMaxTiles);
+  if (halo < 0) return fail(PTYCHO_E_ARG, "negative halo");
+  if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  std::vector<ptycho::TileDesc> table(ntiles);
+  for (int k = 0; k < ntiles; ++k) {
+    const ptycho_tile_desc& t = tiles[k];
+    if (t.ty0 < 0 || t.tx0 < 0 || t.ty1 > H || t.tx1 > W || t.ty0 >= t.ty1 || t.tx0 >= t.tx1)
+      return fail(PTYCHO_E_SHAPE, "tile %d: [%d,%d)x[%d,%d) not inside %dx%d", k, t.ty0, t.ty1, t.tx0, t.tx1, H, W);
+    const int ey0 = std::max(t.ty0 - halo, 0), ex0 = std::max(t.tx0 - halo, 0);
+    const int ey1 = std::min(t.ty1 + halo, H), ex1 = std::min(t.tx1 + halo, W);
+    if (t.ey0 != ey0 || t.ex0 != ex0 || t.eh != ey1 - ey0 || t.ew != ex1 - ex0)
+      return fail(PTYCHO_E_SHAPE, "tile %d: extended box is not the tile grown by halo %d", k, halo);
+    if (t.eh < ctx->M || t.ew < ctx->M) return fail(PTYCHO_E_HALO, "tile %d: extended box smaller than a window", k);
+    if (!t.grad || t.grad == obj) return fail(PTYCHO_E_ARG, "tile %d: bad gradient buffer", k);
+    ptycho::TileDesc& d = table[k];
+    d.ty0 = t.ty0; d.ty1 = t.ty1; d.tx0 = t.tx0; d.tx1 = t.tx1;
+    d.ey0 = t.ey0; d.ex0 = t.ex0; d.eh = t.eh; d.ew = t.ew;
+    d.grad = static_cast<float2*>(t.grad);
+    d.gslice = static_cast<long long>(t.eh) * t.ew;
+    d.gld = t.ew;
+  }
+  // Upload the table only when it changed (a walk passes the same tiles every step).  The copy is
+  // stream-ordered after launches that still read the old table, and the host copy it reads is
+  // kept unchanged until the stream has passed it.
+  const bool same = ctx->h_tiles.size() == table.size() &&
+                    std::memcmp(ctx->h_tiles.data(), table.data(), table.size() * sizeof(ptycho::TileDesc)) == 0;
+  if (!same) {
+    PT_HIP(hipStreamSynchronize(ctx->stream));  // the previous upload has been read
+    ctx->h_tiles.swap(table);
+    PT_HIP(hipMemcpyAsync(ctx->d_tiles, ctx->h_tiles.data(), ntiles * sizeof(ptycho::TileDesc),
+                          hipMemcpyHostToDevice, ctx->stream));
+  }
+  const bool acc = (flags & PTYCHO_ACCUMULATE) != 0;
+  if (!acc) PT_HIP(ptycho::launch_zero_tiles(ctx->d_tiles, ntiles, ctx->S, ctx->stream));
+  ptycho::KernelArgs a = base_args(ctx);
+  a.n = n;
+  a.obj = static_cast<const float2*>(obj);
+  a.slice_stride = slice_stride;
+  a.ld = ld;
+  a.bh = H;
+  a.bw = W;
+  a.oob_flag = PTYCHO_STATUS_HALO;
+  a.probe = static_cast<const float2*>(probe);
+  a.pos = pos;
+  a.meas = meas;
+  a.loss_pos = loss_per_pos;
+  a.tiles = ctx->d_tiles;
+  a.tile_of_pos = tile_of_pos;
+  a.ntiles = ntiles;
+  if (n > 0) {
+    rc = launch_fused_timed(ctx, a, ptycho::kModeLossGrad);
+    if (rc != PTYCHO_OK) return rc;
+  }
+  PT_HIP(ptycho::launch_finalize_loss(ctx->d_loss, n, loss, acc, ctx->stream));
+  return PTYCHO_OK;
 }
 
 int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, int32_t ex0, int32_t eh,

@@ -21,6 +21,15 @@ __host__ __device__ constexpr int ws_slots(int S, int ck) {
                 : ((S - 1) / ck) + ((ck < S ? ck : S) - 1) + (((S - 1) / ck) > 0 && ck > 1 ? 1 : 0);
 }
 
+// Device copy of a tile descriptor (all tiles of one launch).
+struct TileDesc {
+  int ty0, ty1, tx0, tx1;  // tile, global pixels
+  int ey0, ex0, eh, ew;    // extended box
+  float2* grad;            // [S][eh][ew] dense
+  long long gslice, gld;
+};
+constexpr int kMaxTiles = 4096;
+
 struct KernelArgs {
   int M, S, n;
   // object window source: element (s, y, x) at obj[s*slice_stride + y*ld + x], y, x local to the box
@@ -46,6 +55,10 @@ struct KernelArgs {
   unsigned* status;
   const double* grad_scale;  // nullable device scalar multiplying the gradient
   float2* probe_part;    // probe-gradient mode: per-workgroup partial sums, grid * M*M (layout-A order)
+  // all-tiles mode (tiles != nullptr): the gradient of position p goes to tiles[tile_of_pos[p]]
+  const TileDesc* tiles;
+  const int* tile_of_pos;
+  int ntiles;
 };
 
 // One reconstruction of a batch (device copy of the public descriptor plus
@@ -90,6 +103,7 @@ hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);
+hipError_t launch_zero_tiles(const TileDesc* tiles, int ntiles, int S, hipStream_t st);
 hipError_t launch_probe_reduce(const float2* part, int parts, int M, float2* probe_grad, bool accumulate,
                                hipStream_t st);
 hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const float* V, long long vs, long long vld,

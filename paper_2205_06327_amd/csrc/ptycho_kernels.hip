@@ -524,7 +524,31 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     if (p < 0) break;
     const int gy = a.pos[2 * p], gx = a.pos[2 * p + 1];
     const int y0 = gy - a.oy, x0 = gx - a.ox;
-    if (!check_window(a, y0, x0, gy, gx)) {
+    bool ok;
+    if (a.tiles != nullptr) {  // all-tiles mode: the owning tile's box and gradient buffer (uniform)
+      const int tk = a.tile_of_pos[p];
+      ok = tk >= 0 && tk < a.ntiles;
+      unsigned flag = 4u;
+      if (ok) {
+        const TileDesc& T = a.tiles[tk];
+        const int cy = gy + M / 2, cx = gx + M / 2;
+        ok = cy >= T.ty0 && cy < T.ty1 && cx >= T.tx0 && cx < T.tx1;
+        if (ok) {
+          ok = gy >= T.ey0 && gx >= T.ex0 && gy + M <= T.ey0 + T.eh && gx + M <= T.ex0 + T.ew;
+          flag = 2u;
+        }
+        if (ok) {
+          jb.grad = T.grad + static_cast<long long>(gy - T.ey0) * T.gld + (gx - T.ex0);
+          jb.gld = T.gld;
+          jb.gslice = T.gslice;
+        }
+      }
+      if (!ok && threadIdx.x == 0) atomicOr(a.status, flag);
+    } else {
+      ok = check_window(a, y0, x0, gy, gx);
+      jb.grad = a.grad + static_cast<long long>(y0) * a.gld + x0;
+    }
+    if (!ok) {
       if (LOSS && threadIdx.x == 0) {
         a.loss_work[p] = 0.0;
         if (a.loss_pos != nullptr) a.loss_pos[p] = 0.0;
@@ -534,7 +558,6 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
     jb.win = a.obj + static_cast<long long>(y0) * a.ld + x0;
     jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
     jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
-    jb.grad = a.grad + static_cast<long long>(y0) * a.gld + x0;
     const double f = run_position<G, MODE, G::M == 128, true>(jb, sh, twb, hy, ws, L);
     if (LOSS && L.tid == 0) {
       a.loss_work[p] = f;
@@ -756,6 +779,15 @@ __global__ void potential_kernel(int mode, float sigma, int H, int W, const floa
   }
 }
 
+// Zeroes every tile gradient of an all-tiles launch (blockIdx.y = tile).
+__global__ void zero_tiles_kernel(const TileDesc* __restrict__ tiles, int S) {
+  const TileDesc& T = tiles[blockIdx.y];
+  const long long total = static_cast<long long>(S) * T.eh * T.ew;  // dense buffers
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < total;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    T.grad[i] = make_float2(0.f, 0.f);
+}
+
 // probe_grad[y][x] (+)= sum over the workgroups' partial sums, which hold pixel
 // (y, x) = (Y2*r + n2, x) at index r*T + n2*M + x (layout A).  The sum runs in
 // workgroup order, so the result does not depend on timing.
@@ -878,6 +910,12 @@ hipError_t launch_potential(int mode, float sigma, int S, int H, int W, const fl
   const unsigned rows = static_cast<unsigned>(H < 1024 ? H : 1024);
   hipLaunchKernelGGL(potential_kernel, dim3(rows, static_cast<unsigned>(S)), dim3(256), 0, st, mode, sigma, H, W, V,
                      vs, vld, t_out, t_in, ts, tld, g, gs, gld, gv, gvs, gvld);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_tiles(const TileDesc* tiles, int ntiles, int S, hipStream_t st) {
+  if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_tiles_kernel, dim3(256, static_cast<unsigned>(ntiles)), dim3(256), 0, st, tiles, S);
   return hipGetLastError();
 }
 

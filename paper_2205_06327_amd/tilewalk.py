@@ -167,6 +167,56 @@ class ResidentTileWalk:
         return self.tile_loss
 
 
+class AllTilesWalk:
+    """Every tile's gradient in one persistent launch (ptycho_tiles_grad), then the stitch.
+
+    The same decomposition as ResidentTileWalk -- each position adds into the
+    gradient buffer of the tile that owns it, on that tile's extended box --
+    but the tiles' launches become one, as a mesh of devices would run them
+    side by side: no tail per tile and one launch to time.  It holds every
+    tile's buffer (the sum of the extended boxes).
+    """
+
+    def __init__(self, ctx: B.Context, plan: TileWalk, device="cuda:0"):
+        import torch
+        self.ctx, self.plan = ctx, plan
+        S = ctx.S
+        ctx.reserve(max(plan.n, 1))
+        self.pos = torch.tensor(plan.pos_sorted, dtype=torch.int32, device=device)
+        owner = np.empty(plan.n, dtype=np.int32)
+        for p in plan.plans:
+            owner[p.lo:p.hi] = p.index
+        self.tile_of_pos = torch.tensor(owner, dtype=torch.int32, device=device)
+        self.bufs = [torch.empty((S, p.box[2], p.box[3]), dtype=torch.complex64, device=device) for p in plan.plans]
+        self.tiles = [(p.tile, p.box, self.bufs[k]) for k, p in enumerate(plan.plans)]
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    @property
+    def lanes(self) -> int:
+        return 1
+
+    def device_bytes(self) -> int:
+        return sum(b.numel() * b.element_size() for b in self.bufs)
+
+    def profile(self, enable: bool = True) -> None:
+        self.ctx.profile(enable)
+
+    def profile_read(self):
+        return self.ctx.profile_read()
+
+    def check(self) -> int:
+        return self.ctx.check()
+
+    def step(self, obj, probe, meas_sorted, grad):
+        """grad <- sum of the embedded tile gradients; returns the total loss (float64 [1])."""
+        B.ptycho_zero_gradient(self.ctx, grad)
+        B.ptycho_tiles_grad(self.ctx, obj, self.tiles, self.plan.halo, self.tile_of_pos, probe, self.pos,
+                            meas_sorted, loss=self.loss)
+        for k, p in enumerate(self.plan.plans):
+            B.ptycho_tile_accumulate(self.ctx, self.bufs[k], p.box, grad)
+        return self.loss
+
+
 class StreamingTileWalk:
     """Decomposed gradient with object, measurements and the global gradient in pinned host memory.
 

@@ -219,3 +219,41 @@ def test_alg1_walk_matches_oracle(torch_cuda, batch, T):
     writes = 2 * (walk.steps + -(-walk.steps // T))
     tol = 1e-4 + writes * 2.0 ** -24 * np.linalg.norm(V0) / np.linalg.norm(dV)
     assert rel_l2(V.cpu().numpy() - V0, dV) <= tol
+
+
+def test_all_tiles_in_one_launch(torch_cuda):
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.tilewalk import AllTilesWalk, ResidentTileWalk, TileWalk
+    spec = ps.with_overrides(tiled_spec(), tiles=(3, 3))
+    say("all tiles' gradients in one launch vs the tile-by-tile walk and the oracle")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
+    g_all = torch.empty_like(t["obj"])
+    g_lanes = torch.empty_like(t["obj"])
+    walk = AllTilesWalk(ctx, plan)
+    for _ in range(2):
+        l_all = float(walk.step(t["obj"], t["probe"], meas_sorted, g_all).item())
+    assert walk.check() == 0
+    l_lanes = float(ResidentTileWalk(ctx, plan).step(t["obj"], t["probe"], meas_sorted, g_lanes).sum())
+    torch.cuda.synchronize()
+    assert rel_l2(g_all.cpu().numpy(), g_lanes.cpu().numpy()) <= 1e-6
+    assert abs(l_all - l_lanes) <= 1e-9 * l_lanes
+    G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+    assert rel_l2(g_all.cpu().numpy(), G_ref) <= 1e-4
+    for k, p in enumerate(plan.plans):  # each tile buffer against the oracle's tile gradient
+        ty, tx = divmod(k, spec.tiles[1])
+        ref = oracle.tile_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"], spec.tiles, spec.halo,
+                                   ty, tx)
+        assert rel_l2(walk.bufs[k].cpu().numpy(), ref["grad"]) <= 1e-4, k
+    # a position given to the wrong tile is skipped and reported on the device
+    bad = walk.tile_of_pos.clone()
+    bad[0] = (int(bad[0]) + 4) % 9
+    pt.ptycho_tiles_grad(ctx, t["obj"], walk.tiles, spec.halo, bad, t["probe"], walk.pos, meas_sorted)
+    with pytest.raises(pt.PtychoError) as e:
+        ctx.check()
+    assert e.value.name == "PTYCHO_E_ASSIGN"
+    assert ctx.check() == 0  # reading the status clears it
