@@ -257,3 +257,30 @@ def test_all_tiles_in_one_launch(torch_cuda):
         ctx.check()
     assert e.value.name == "PTYCHO_E_ASSIGN"
     assert ctx.check() == 0  # reading the status clears it
+
+
+def test_tiles_grad_host_validation(torch_cuda):
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.tilewalk import AllTilesWalk, TileWalk
+    spec = ps.with_overrides(tiled_spec(), tiles=(2, 2))
+    say("ptycho_tiles_grad rejects bad tile tables on the host")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    walk = AllTilesWalk(ctx, plan)
+    meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
+    (tile, box, g) = walk.tiles[0]
+    bad_box = [((tile), (box[0], box[1], box[2] - 1, box[3]), g[:, :-1, :].contiguous())] + walk.tiles[1:]
+    with pytest.raises(pt.PtychoError) as e:
+        pt.ptycho_tiles_grad(ctx, t["obj"], bad_box, spec.halo, walk.tile_of_pos, t["probe"], walk.pos, meas_sorted)
+    assert e.value.name == "PTYCHO_E_SHAPE"
+    with pytest.raises(pt.PtychoError) as e:
+        pt.ptycho_tiles_grad(ctx, t["obj"], [], spec.halo, walk.tile_of_pos, t["probe"], walk.pos, meas_sorted)
+    assert e.value.name == "PTYCHO_E_ARG"
+    outside = [((0, spec.W + 1, 0, 10), box, g)] + walk.tiles[1:]
+    with pytest.raises(pt.PtychoError) as e:
+        pt.ptycho_tiles_grad(ctx, t["obj"], outside, spec.halo, walk.tile_of_pos, t["probe"], walk.pos, meas_sorted)
+    assert e.value.name == "PTYCHO_E_SHAPE"
+    assert ctx.check() == 0  # nothing was enqueued
