@@ -48,8 +48,8 @@ def bf_propagator(M, lam, dz, pixel):
     return np.exp(-1j * np.pi * lam * dz * (k[:, None] ** 2 + k[None, :] ** 2))
 
 
-def bf_intensity(obj, probe, y0, x0, lam, dz, pixel):
-    """Multislice by explicit DFT sums: transmit, propagate between slices, detect."""
+def bf_far_field(obj, probe, y0, x0, lam, dz, pixel):
+    """Multislice by explicit DFT sums: transmit, propagate between slices, far field."""
     M = probe.shape[0]
     Hb = bf_propagator(M, lam, dz, pixel)
     psi = probe.astype(np.complex128)
@@ -58,7 +58,11 @@ def bf_intensity(obj, probe, y0, x0, lam, dz, pixel):
         phi = psi * obj[s, y0:y0 + M, x0:x0 + M]
         if s < S - 1:
             psi = bf_idft2(Hb * bf_dft2(phi))
-    return np.abs(bf_dft2(phi)) ** 2
+    return bf_dft2(phi)
+
+
+def bf_intensity(obj, probe, y0, x0, lam, dz, pixel):
+    return np.abs(bf_far_field(obj, probe, y0, x0, lam, dz, pixel)) ** 2
 
 
 def rand_complex(rng, shape, lo=0.5, hi=1.5):
@@ -234,6 +238,40 @@ def test_central_finite_differences():
                  - oracle.loss_and_gradient(om, probe, pos, meas, H)[0]) / (2 * h)
             fd[idx] += d * unit
     np.testing.assert_allclose(G, fd, rtol=0, atol=2e-6 * np.abs(G).max())
+
+
+@pytest.mark.parametrize("S", [1, 3])
+def test_adjoint_dot_product(S):
+    """Eq. 2 as an adjoint identity.  With the other slices fixed, the far field
+    of one position is complex-linear in slice s's window (and in the probe), so
+    dPsi = J_s dt exactly, with J_s dt the far field of the object whose window
+    on slice s is replaced by dt.  Since dF = Re sum conj(g) dPsi with
+    g = 2(|Psi| - a) Psi/|Psi|, the gradient G_s must satisfy
+    Re<g, J_s dt> = Re<G_s, dt> for every dt.  J_s dt is evaluated by explicit
+    DFT sums, so a missing conjugate of H, a wrong M^2, a swapped slice or a
+    conjugated incident wave in the oracle's adjoint breaks the identity."""
+    rng = np.random.default_rng(31 + S)
+    M, W, y0, x0 = 8, 12, 3, 2
+    obj = rand_complex(rng, (S, W, W))
+    probe = rand_complex(rng, (M, M))
+    H = oracle.fresnel_propagator(M, LAM, DZ, PIX)
+    far = bf_far_field(obj, probe, y0, x0, LAM, DZ, PIX)
+    meas = rng.uniform(0.2, 2.0, (M, M)) * np.abs(far) ** 2
+    g = 2.0 * (np.abs(far) - np.sqrt(meas)) * far / np.abs(far)
+    _, grads = oracle.position_loss_and_patch_gradients(obj, probe, y0, x0, meas, H)
+    for s in range(S):
+        dt = rand_complex(rng, (M, M))
+        o2 = obj.copy()
+        o2[s, y0:y0 + M, x0:x0 + M] = dt
+        lhs = np.real(np.vdot(g, bf_far_field(o2, probe, y0, x0, LAM, DZ, PIX)))
+        rhs = np.real(np.vdot(grads[s], dt))
+        scale = np.linalg.norm(grads[s]) * np.linalg.norm(dt)
+        assert abs(lhs - rhs) <= 1e-11 * scale, (s, lhs, rhs)
+    dP = rand_complex(rng, (M, M))
+    lhs = np.real(np.vdot(g, bf_far_field(obj, dP, y0, x0, LAM, DZ, PIX)))
+    GP = oracle.probe_gradient(obj, probe, np.array([[y0, x0]]), meas[None], H)
+    rhs = np.real(np.vdot(GP, dP))
+    assert abs(lhs - rhs) <= 1e-11 * np.linalg.norm(GP) * np.linalg.norm(dP), (lhs, rhs)
 
 
 def test_torch_autograd_cross_check():
