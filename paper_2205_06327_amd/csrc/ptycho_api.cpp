@@ -209,7 +209,8 @@ int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, d
     return fail(PTYCHO_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
   }
   c->bytes = static_cast<int64_t>(2 * M * sizeof(float2) + c->capacity * sizeof(double) + sizeof(unsigned) +
-                                  ws_elems * sizeof(float2) + static_cast<size_t>(c->grid) * M * M * sizeof(float2));
+                                  ws_elems * sizeof(float2) + static_cast<size_t>(c->grid) * M * M * sizeof(float2) +
+                                  ptycho::kMaxTiles * sizeof(ptycho::TileDesc));
   if ((e = hipMemcpy(c->d_tw, tw.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(c->d_h, h.data(), M * sizeof(float2), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_status, 0, sizeof(unsigned))) != hipSuccess || (e = hipDeviceSynchronize()) != hipSuccess) {
