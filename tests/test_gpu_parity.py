@@ -179,6 +179,40 @@ def test_device_side_window_checks(torch_cuda):
     assert ctx.check() == 0  # cleared
 
 
+def test_degenerate_inputs(torch_cuda):
+    """Degenerate cases of the method, for both window sizes: a zero probe (|Psi| = 0 everywhere,
+    so u = 0: the loss is the sum of the measurements and the gradient vanishes exactly, no NaN),
+    zero measurements (the loss is the total intensity) and dz = 0 (the propagator is the identity,
+    so the slices act as their product), each against the oracle."""
+    import paper_2205_06327_amd as pt
+    import torch
+    for M, base in ((128, "ms8-1024-m128"), (64, "2d-256-m64")):
+        spec = ps.with_overrides(ps.workload(base), W=2 * M, ny=2, nx=3, step=M // 8, S=3, noise=True)
+        say(f"degenerate inputs, M={M}: zero probe, zero measurements, dz = 0")
+        d = problem(spec)
+        t = to_dev(d)
+        ctx = context(spec, spec.n)
+        loss, G = pt.ptycho_loss_grad(ctx, t["obj"], torch.zeros_like(t["probe"]), t["pos"], t["meas"])
+        assert ctx.check() == 0
+        expect = float(d["meas"].astype(np.float64).sum())
+        assert abs(float(loss.item()) - expect) <= 1e-6 * expect
+        assert float(G.abs().max()) == 0.0
+        zero = np.zeros_like(d["meas"])
+        loss, G = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], torch.zeros_like(t["meas"]))
+        L_ref, _, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], zero, d["H"])
+        assert abs(float(loss.item()) - L_ref) <= TOL_L * L_ref
+        assert rel_l2(G.cpu().numpy(), G_ref) <= TOL_G
+        ctx0 = pt.Context(M, spec.S, spec.wavelength_A, 0.0, spec.pixel_A, spec.n)
+        H0 = oracle.fresnel_propagator(M, spec.wavelength_A, 0.0, spec.pixel_A)
+        I = pt.ptycho_forward(ctx0, t["obj"], t["probe"], t["pos"])
+        loss, G = pt.ptycho_loss_grad(ctx0, t["obj"], t["probe"], t["pos"], t["meas"])
+        assert ctx0.check() == 0
+        L_ref, _, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], H0)
+        assert rel_l2(I.cpu().numpy(), oracle.forward(d["obj_eval"], d["probe"], d["pos"], H0)) <= TOL_I
+        assert abs(float(loss.item()) - L_ref) <= TOL_L * L_ref
+        assert rel_l2(G.cpu().numpy(), G_ref) <= TOL_G
+
+
 def test_checkpointed_wave_recomputation(torch_cuda):
     """Keeping only every k-th incident wave and recomputing the others in the adjoint sweep
     gives the same losses (the forward sweep is unchanged) and the same gradient up to the
