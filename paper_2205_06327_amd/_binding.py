@@ -170,19 +170,38 @@ def _stream_ptr() -> int:
     return int(torch.cuda.current_stream().cuda_stream)
 
 
-def _obj_geometry(obj) -> Tuple[int, int, int, int, int]:
-    """(S, H, W, slice_stride, ld) of a complex64 [S, H, W] tensor with unit column stride."""
+def _on_device(t, name: str) -> None:
+    """Every pointer handed to the library must be device memory of the current device: a host
+    pointer or another device's memory would reach the kernels as an invalid address."""
     torch = _torch()
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.device.index is not None and t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is on {t.device}, the current device is cuda:{torch.cuda.current_device()}")
+
+
+def _obj_geometry(obj) -> Tuple[int, int, int, int, int]:
+    """(S, H, W, slice_stride, ld) of a complex64 [S, H, W] device tensor with unit column stride."""
+    torch = _torch()
+    _on_device(obj, "object")
     if obj.dtype != torch.complex64 or obj.dim() != 3 or obj.stride(2) != 1:
         raise ValueError("object must be complex64 [S, H, W] with unit stride along W")
     S, H, W = obj.shape
     return S, H, W, obj.stride(0), obj.stride(1)
 
 
+def _need_pos(pos) -> int:
+    """Positions: int32 [n, 2] contiguous device tensor; returns n."""
+    torch = _torch()
+    _need(pos, torch.int32, None, "pos")
+    if pos.dim() != 2 or pos.shape[1] != 2:
+        raise ValueError(f"pos must have shape [n, 2], got {tuple(pos.shape)}")
+    return int(pos.shape[0])
+
+
 def _need(t, dtype, shape=None, name="tensor"):
     torch = _torch()
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
-        raise ValueError(f"{name} must be a CUDA tensor")
+    _on_device(t, name)
     if t.dtype != dtype:
         raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
@@ -257,7 +276,7 @@ def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
     _need(probe, torch.complex64, (M, M), "probe")
-    _need(pos, torch.int32, None, "pos")
+    _need_pos(pos)
     n = pos.shape[0]
     if intens is None:
         intens = torch.empty((n, M, M), dtype=torch.float32, device=obj.device)
@@ -276,7 +295,7 @@ def ptycho_loss(ctx: Context, obj, probe, pos, meas, loss=None, loss_per_pos=Non
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
     _need(probe, torch.complex64, (M, M), "probe")
-    _need(pos, torch.int32, None, "pos")
+    _need_pos(pos)
     n = pos.shape[0]
     _need(meas, torch.float32, (n, M, M), "meas")
     if loss is None:
@@ -307,7 +326,7 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
     _need(probe, torch.complex64, (M, M), "probe")
-    _need(pos, torch.int32, None, "pos")
+    _need_pos(pos)
     n = pos.shape[0]
     _need(meas, torch.float32, (n, M, M), "meas")
     if grad is None:
@@ -354,7 +373,7 @@ def ptycho_tile_grad(ctx: Context, obj_ext, box, tile, halo: int, H: int, W: int
         raise ValueError("obj_ext shape does not match the box or the context")
     M = ctx.M
     _need(probe, torch.complex64, (M, M), "probe")
-    _need(pos, torch.int32, None, "pos")
+    _need_pos(pos)
     n = pos.shape[0]
     _need(meas, torch.float32, (n, M, M), "meas")
     if tile_grad is None:
@@ -380,9 +399,12 @@ def ptycho_tile_accumulate(ctx: Context, tile_grad, box, grad) -> None:
     """grad[:, ey0:ey0+eh, ex0:ex0+ew] += tile_grad (the stitch of the tile walk)."""
     torch = _torch()
     ey0, ex0, eh, ew = box
+    if grad.dim() != 3:
+        raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
     S, H, W = grad.shape
     _need(tile_grad, torch.complex64, (ctx.S, eh, ew), "tile_grad")
-    if grad.dtype != torch.complex64 or grad.stride(2) != 1 or S != ctx.S:
+    _on_device(grad, "grad")
+    if grad.dtype != torch.complex64 or grad.dim() != 3 or grad.stride(2) != 1 or S != ctx.S:
         raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
     ctx._bind_stream()
     _check(lib().ptycho_tile_accumulate(ctx.handle, c_vp(tile_grad.data_ptr()), ey0, ex0, eh, ew, H, W,
@@ -398,7 +420,8 @@ def ptycho_box_exchange(ctx: Context, src, src_origin, dst, dst_origin, replace:
     are complex64 [S, h, w] views with unit stride along w, in separate memory."""
     torch = _torch()
     for t, name in ((src, "src"), (dst, "dst")):
-        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64:
+        _on_device(t, name)
+        if t.dtype != torch.complex64:
             raise ValueError(f"{name} must be a complex64 CUDA tensor")
         if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != ctx.S:
             raise ValueError(f"{name} must be [S, h, w] with unit stride along w")
@@ -414,7 +437,8 @@ def ptycho_box_axpy(ctx: Context, alpha: float, src, src_origin, dst, dst_origin
     """dst += alpha * src on the overlap of two boxes (same conventions as ptycho_box_exchange)."""
     torch = _torch()
     for t, name in ((src, "src"), (dst, "dst")):
-        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.complex64:
+        _on_device(t, name)
+        if t.dtype != torch.complex64:
             raise ValueError(f"{name} must be a complex64 CUDA tensor")
         if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != ctx.S:
             raise ValueError(f"{name} must be [S, h, w] with unit stride along w")
@@ -427,7 +451,8 @@ def ptycho_box_axpy(ctx: Context, alpha: float, src, src_origin, dst, dst_origin
 
 def _plane(t, dtype, S, name):
     torch = _torch()
-    if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != dtype:
+    _on_device(t, name)
+    if t.dtype != dtype:
         raise ValueError(f"{name} must be a {dtype} CUDA tensor")
     if t.dim() != 3 or t.stride(2) != 1 or t.shape[0] != S:
         raise ValueError(f"{name} must be [S, H, W] with unit stride along W")
@@ -478,7 +503,7 @@ def ptycho_tiles_grad(ctx: Context, obj, tiles, halo: int, tile_of_pos, probe, p
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
     _need(probe, torch.complex64, (M, M), "probe")
-    _need(pos, torch.int32, None, "pos")
+    _need_pos(pos)
     n = pos.shape[0]
     _need(tile_of_pos, torch.int32, (n,), "tile_of_pos")
     _need(meas, torch.float32, (n, M, M), "meas")
@@ -519,6 +544,7 @@ def ptycho_copy_box(ctx: Context, src, dst) -> None:
 def ptycho_zero_gradient(ctx: Context, grad) -> None:
     """grad[...] = 0 with the library's fill kernel."""
     torch = _torch()
+    _on_device(grad, "grad")
     if grad.dtype != torch.complex64 or grad.dim() != 3 or grad.stride(2) != 1 or grad.shape[0] != ctx.S:
         raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
     ctx._bind_stream()

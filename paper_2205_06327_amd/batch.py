@@ -65,10 +65,11 @@ class Recon:
         S, H, W, ss, ld = B._obj_geometry(obj)
         M = probe.shape[0]
         B._need(probe, torch.complex64, (M, M), "probe")
-        B._need(pos, torch.int32, None, "pos")
-        B._need(meas, torch.float32, (pos.shape[0], M, M), "meas")
+        n = B._need_pos(pos)
+        B._need(meas, torch.float32, (n, M, M), "meas")
         if grad is None:
             grad = torch.empty_strided(obj.shape, obj.stride(), dtype=torch.complex64, device=obj.device)
+        B._on_device(grad, "grad")
         if grad.shape != obj.shape or grad.stride() != obj.stride() or grad.dtype != torch.complex64:
             raise ValueError("grad must have the object's shape and strides")
         self.obj, self.probe, self.pos, self.meas, self.grad = obj, probe, pos, meas, grad
@@ -120,6 +121,10 @@ class Batch:
         return int(_lib().ptycho_batch_get_grid(self._h, int(M)))
 
     def loss_grad(self, losses=None) -> None:
+        """One batched gradient launch; losses (optional float64 [nrecon] device tensor) receives the losses."""
+        if losses is not None:
+            import torch
+            B._need(losses, torch.float64, (len(self.recons),), "losses")
         ptr = ctypes.c_void_p(losses.data_ptr()) if losses is not None else ctypes.c_void_p(0)
         B._check(_lib().ptycho_batch_loss_grad(self._h, ptr))
 

@@ -140,3 +140,18 @@ def test_new_entry_points_reject_a_null_context():
     assert L.ptycho_box_axpy(None, 1, ctypes.c_float(1.0), ctypes.c_void_p(8), 0, 0, 1, 1, 1, 1,
                              ctypes.c_void_p(16), 0, 0, 1, 1, 1, 1) == -1
     assert b"null context" in L.ptycho_last_error()
+
+
+def test_binding_rejects_host_tensors_and_bad_position_shapes():
+    """Host-side argument checks of the binding, before any library call: a host tensor or a
+    position array that is not [n, 2] would reach the kernels as invalid device memory."""
+    torch = pytest.importorskip("torch")
+    from paper_2205_06327_amd import _binding as B
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        B._obj_geometry(torch.zeros((2, 8, 8), dtype=torch.complex64))
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        B._need(torch.zeros(4, dtype=torch.float32), torch.float32, None, "meas")
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        B._need_pos(torch.zeros((3, 2), dtype=torch.int32))
+    with pytest.raises(ValueError, match="CUDA tensor"):
+        B._on_device(np.zeros(3), "x")

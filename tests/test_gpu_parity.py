@@ -177,6 +177,11 @@ def test_device_side_window_checks(torch_cuda):
     assert e.value.name == "PTYCHO_E_BOUNDS"
     assert float(I[1].max()) == -1.0 and float(I[0].min()) >= 0.0
     assert ctx.check() == 0  # cleared
+    # the binding refuses position arrays that are not [n, 2] and host tensors before any launch
+    with pytest.raises(ValueError):
+        pt.ptycho_forward(ctx, t["obj"], t["probe"], t["pos"].reshape(-1).contiguous())
+    with pytest.raises(ValueError):
+        pt.ptycho_forward(ctx, t["obj"].cpu(), t["probe"], t["pos"])
 
 
 def test_degenerate_inputs(torch_cuda):
