@@ -43,7 +43,13 @@
  *
  * Errors: every call returns PTYCHO_OK (0) or a negative code; a call that
  * fails host validation enqueues nothing.  ptycho_last_error() returns a
- * thread-local message for the last failure.  Windows that leave the object,
+ * thread-local message for the last failure.  Host validation includes the
+ * caller's buffers: each must be device memory of the context's device,
+ * managed memory or pinned host memory (else PTYCHO_E_ARG: a pageable host
+ * pointer would reach the kernels as an invalid address), and the bytes a
+ * call addresses from it must lie inside its allocation where the runtime
+ * knows the allocation (else PTYCHO_E_SHAPE).  ptycho_copy_box is the
+ * exception: it also takes pageable host memory.  Windows that leave the object,
  * the extended tile or the tile (conditions only visible on the device because
  * positions live in device memory) are skipped by the kernels without any
  * memory access and recorded in a device status word; ptycho_check()

@@ -111,6 +111,58 @@ int check_object_args(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W
   return PTYCHO_OK;
 }
 
+// Host-side check of a caller buffer the kernels will address: it must be device memory of the
+// context's device, managed memory or pinned host memory, and, where the runtime knows the
+// allocation, [p, p + bytes) must lie inside it.  A pageable host pointer, another device's
+// memory or an overrun would otherwise reach the kernels as an invalid address.  Memory the
+// runtime reports without an address range (e.g. virtual-memory mappings) passes on its type.
+int check_buffer(int device, const void* p, size_t bytes, const char* what) {
+  if (!p || bytes == 0) return PTYCHO_OK;  // presence is checked by the callers
+  hipPointerAttribute_t at{};
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess || at.type == hipMemoryTypeUnregistered) {
+    (void)hipGetLastError();
+    return fail(PTYCHO_E_ARG, "%s is not device-accessible memory (pageable host memory?)", what);
+  }
+  if (at.type == hipMemoryTypeDevice && at.device != device)
+    return fail(PTYCHO_E_ARG, "%s is on device %d, the context on device %d", what, at.device, device);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess) {
+    const size_t off = static_cast<size_t>(static_cast<const char*>(p) - static_cast<const char*>(base));
+    if (off > size || bytes > size - off)
+      return fail(PTYCHO_E_SHAPE, "%s: %zu bytes from offset %zu overrun its %zu-byte allocation", what, bytes, off,
+                  size);
+  } else {
+    (void)hipGetLastError();
+  }
+  return PTYCHO_OK;
+}
+
+// Elements spanned by a [S][h][w] view with strides (slice_stride, ld), 0 when empty.
+size_t span_elems(int64_t S, int64_t h, int64_t w, int64_t slice_stride, int64_t ld) {
+  if (S <= 0 || h <= 0 || w <= 0) return 0;
+  return static_cast<size_t>((S - 1) * (S > 1 ? slice_stride : 0) + (h - 1) * ld + w);
+}
+
+#define PT_BUF(dev, p, bytes, what)                               \
+  do {                                                            \
+    int rc_ = check_buffer((dev), (p), (bytes), (what));          \
+    if (rc_ != PTYCHO_OK) return rc_;                             \
+  } while (0)
+
+// The object, probe, positions and (optional) patterns of a position call.
+int check_position_buffers(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas) {
+  if (n == 0) return PTYCHO_OK;
+  const size_t M2 = static_cast<size_t>(c->M) * c->M;
+  PT_BUF(c->device, obj, span_elems(c->S, H, W, slice_stride, ld) * sizeof(float2), "object");
+  PT_BUF(c->device, probe, M2 * sizeof(float2), "probe");
+  PT_BUF(c->device, pos, 2 * static_cast<size_t>(n) * sizeof(int32_t), "positions");
+  PT_BUF(c->device, meas, static_cast<size_t>(n) * M2 * sizeof(float), "measurements");
+  return PTYCHO_OK;
+}
+
 ptycho::KernelArgs base_args(const ptycho_ctx* c) {
   ptycho::KernelArgs a{};
   a.M = c->M;
@@ -256,6 +308,9 @@ int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64
   if (rc != PTYCHO_OK) return rc;
   if (n == 0) return PTYCHO_OK;
   if (!intens) return fail(PTYCHO_E_ARG, "null intensity output");
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, nullptr);
+  if (rc != PTYCHO_OK) return rc;
+  PT_BUF(ctx->device, intens, static_cast<size_t>(n) * ctx->M * ctx->M * sizeof(float), "intensities");
   ptycho::KernelArgs a = base_args(ctx);
   a.n = n;
   a.obj = static_cast<const float2*>(obj);
@@ -293,6 +348,13 @@ int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t 
   if (static_cast<int64_t>(grad_ld) * ctx->M >= (int64_t(1) << 31))
     return fail(PTYCHO_E_SHAPE, "gradient row stride too large");  // window row offsets are 32-bit
   if (grad == obj) return fail(PTYCHO_E_ARG, "gradient aliases the object");
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  if (rc != PTYCHO_OK) return rc;
+  PT_BUF(ctx->device, grad, span_elems(ctx->S, H, W, grad_slice_stride, grad_ld) * sizeof(float2), "gradient");
+  PT_BUF(ctx->device, loss, sizeof(double), "loss");
+  PT_BUF(ctx->device, loss_per_pos, static_cast<size_t>(n) * sizeof(double), "per-position losses");
+  PT_BUF(ctx->device, probe_grad, static_cast<size_t>(ctx->M) * ctx->M * sizeof(float2), "probe gradient");
+  PT_BUF(ctx->device, grad_scale, sizeof(double), "gradient scale");
   ptycho::KernelArgs a = base_args(ctx);
   a.n = n;
   a.obj = static_cast<const float2*>(obj);
@@ -323,6 +385,10 @@ int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t 
   if (!loss) return fail(PTYCHO_E_ARG, "null loss");
   if (n > 0 && !meas) return fail(PTYCHO_E_ARG, "null measurements");
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  if (rc != PTYCHO_OK) return rc;
+  PT_BUF(ctx->device, loss, sizeof(double), "loss");
+  PT_BUF(ctx->device, loss_per_pos, static_cast<size_t>(n) * sizeof(double), "per-position losses");
   ptycho::KernelArgs a = base_args(ctx);
   a.n = n;
   a.obj = static_cast<const float2*>(obj);
@@ -384,6 +450,11 @@ int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t 
     return fail(PTYCHO_E_SHAPE, "object strides do not cover the extended box");
   if (static_cast<int64_t>(ld) * ctx->M >= (int64_t(1) << 31)) return fail(PTYCHO_E_SHAPE, "row stride too large");
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  int rc = check_position_buffers(ctx, obj_ext, eh, ew, slice_stride, ld, probe, pos, n, meas);
+  if (rc != PTYCHO_OK) return rc;
+  PT_BUF(ctx->device, tile_grad, static_cast<size_t>(ctx->S) * eh * ew * sizeof(float2), "tile gradient");
+  PT_BUF(ctx->device, loss, sizeof(double), "loss");
+  PT_BUF(ctx->device, loss_per_pos, static_cast<size_t>(n) * sizeof(double), "per-position losses");
   ptycho::KernelArgs a = base_args(ctx);
   a.n = n;
   a.obj = static_cast<const float2*>(obj_ext);
@@ -421,6 +492,11 @@ int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, in
                                                             ptycho::kMaxTiles);
   if (halo < 0) return fail(PTYCHO_E_ARG, "negative halo");
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  if (rc != PTYCHO_OK) return rc;
+  PT_BUF(ctx->device, tile_of_pos, static_cast<size_t>(n) * sizeof(int32_t), "tile indices");
+  PT_BUF(ctx->device, loss, sizeof(double), "loss");
+  PT_BUF(ctx->device, loss_per_pos, static_cast<size_t>(n) * sizeof(double), "per-position losses");
   std::vector<ptycho::TileDesc> table(ntiles);
   for (int k = 0; k < ntiles; ++k) {
     const ptycho_tile_desc& t = tiles[k];
@@ -432,6 +508,7 @@ int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, in
       return fail(PTYCHO_E_SHAPE, "tile %d: extended box is not the tile grown by halo %d", k, halo);
     if (t.eh < ctx->M || t.ew < ctx->M) return fail(PTYCHO_E_HALO, "tile %d: extended box smaller than a window", k);
     if (!t.grad || t.grad == obj) return fail(PTYCHO_E_ARG, "tile %d: bad gradient buffer", k);
+    PT_BUF(ctx->device, t.grad, static_cast<size_t>(ctx->S) * t.eh * t.ew * sizeof(float2), "tile gradient");
     ptycho::TileDesc& d = table[k];
     d.ty0 = t.ty0; d.ty1 = t.ty1; d.tx0 = t.tx0; d.tx1 = t.tx1;
     d.ey0 = t.ey0; d.ex0 = t.ex0; d.eh = t.eh; d.ew = t.ew;
@@ -484,6 +561,8 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
     return fail(PTYCHO_E_SHAPE, "box (%d,%d)+(%d,%d) outside %dx%d", ey0, ex0, eh, ew, H, W);
   if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
     return fail(PTYCHO_E_SHAPE, "gradient strides do not cover %dx%d", H, W);
+  PT_BUF(ctx->device, tile_grad, static_cast<size_t>(ctx->S) * eh * ew * sizeof(float2), "tile gradient");
+  PT_BUF(ctx->device, grad, span_elems(ctx->S, H, W, grad_slice_stride, grad_ld) * sizeof(float2), "gradient");
   float2* g = static_cast<float2*>(grad) + static_cast<int64_t>(ey0) * grad_ld + ex0;
   PT_HIP(ptycho::launch_tile_accumulate(static_cast<const float2*>(tile_grad), ctx->S, eh, ew, g, grad_slice_stride,
                                         grad_ld, ctx->stream));
@@ -508,6 +587,8 @@ int ptycho_potential_transmission(ptycho_ctx* ctx, int32_t H, int32_t W, float s
   if (rc == PTYCHO_OK) rc = check_plane(ctx, H, W, t_slice_stride, t_ld, t, "transmission");
   if (rc != PTYCHO_OK) return rc;
   if (H == 0 || W == 0) return PTYCHO_OK;
+  PT_BUF(ctx->device, V, span_elems(ctx->S, H, W, v_slice_stride, v_ld) * sizeof(float), "potential");
+  PT_BUF(ctx->device, t, span_elems(ctx->S, H, W, t_slice_stride, t_ld) * sizeof(float2), "transmission");
   PT_HIP(ptycho::launch_potential(0, sigma, ctx->S, H, W, V, v_slice_stride, v_ld, static_cast<float2*>(t), nullptr,
                                   t_slice_stride, t_ld, nullptr, 0, 0, nullptr, 0, 0, ctx->stream));
   return PTYCHO_OK;
@@ -523,6 +604,9 @@ int ptycho_potential_gradient(ptycho_ctx* ctx, int32_t H, int32_t W, float sigma
   if (rc == PTYCHO_OK) rc = check_plane(ctx, H, W, gv_slice_stride, gv_ld, grad_V, "potential gradient");
   if (rc != PTYCHO_OK) return rc;
   if (H == 0 || W == 0) return PTYCHO_OK;
+  PT_BUF(ctx->device, t, span_elems(ctx->S, H, W, t_slice_stride, t_ld) * sizeof(float2), "transmission");
+  PT_BUF(ctx->device, grad_t, span_elems(ctx->S, H, W, g_slice_stride, g_ld) * sizeof(float2), "gradient");
+  PT_BUF(ctx->device, grad_V, span_elems(ctx->S, H, W, gv_slice_stride, gv_ld) * sizeof(float), "potential gradient");
   PT_HIP(ptycho::launch_potential(1, sigma, ctx->S, H, W, nullptr, 0, 0, nullptr, static_cast<const float2*>(t),
                                   t_slice_stride, t_ld, static_cast<const float2*>(grad_t), g_slice_stride, g_ld,
                                   grad_V, gv_slice_stride, gv_ld, ctx->stream));
@@ -595,6 +679,8 @@ int box_combine(ptycho_ctx* ctx, int32_t S, const void* src, int32_t sy0, int32_
   };
   const auto a = span(src, sh, sw, s_slice_stride, s_ld), b = span(dst, dh, dw, d_slice_stride, d_ld);
   if (a.first < b.second && b.first < a.second) return fail(PTYCHO_E_ARG, "source and destination share memory");
+  PT_BUF(ctx->device, src, span_elems(S, sh, sw, s_slice_stride, s_ld) * sizeof(float2), "source box");
+  PT_BUF(ctx->device, dst, span_elems(S, dh, dw, d_slice_stride, d_ld) * sizeof(float2), "destination box");
   if (oy0 >= oy1 || ox0 >= ox1) return PTYCHO_OK;  // no overlap
   const int oh = static_cast<int>(oy1 - oy0), ow = static_cast<int>(ox1 - ox0);
   const float2* sp = static_cast<const float2*>(src) + static_cast<int64_t>(oy0 - sy0) * s_ld + (ox0 - sx0);
@@ -626,6 +712,7 @@ int ptycho_zero_gradient(ptycho_ctx* ctx, void* grad, int32_t H, int32_t W, int6
   if (!grad || H < 0 || W < 0) return fail(PTYCHO_E_ARG, "bad gradient buffer");
   if (grad_ld < W || (ctx->S > 1 && grad_slice_stride < static_cast<int64_t>(H) * grad_ld))
     return fail(PTYCHO_E_SHAPE, "strides do not cover %dx%d", H, W);
+  PT_BUF(ctx->device, grad, span_elems(ctx->S, H, W, grad_slice_stride, grad_ld) * sizeof(float2), "gradient");
   PT_HIP(ptycho::launch_zero_slices(static_cast<float2*>(grad), ctx->S, H, W, grad_slice_stride, grad_ld,
                                     ctx->stream));
   return PTYCHO_OK;
@@ -822,6 +909,20 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
     if (!(R.pixel_A > 0) || !std::isfinite(R.wavelength_A) || !std::isfinite(R.dz_A) || !std::isfinite(R.alpha))
       return fail(PTYCHO_E_ARG, "reconstruction %d: invalid physics or step", r);
     total_items += R.n;
+  }
+  if (nrecon > 0) {  // the buffers behind the descriptors (needs the device)
+    int device = 0;
+    PT_HIP(hipGetDevice(&device));
+    for (int r = 0; r < nrecon; ++r) {
+      const ptycho_recon& R = recons[r];
+      const size_t obj_bytes = span_elems(R.S, R.H, R.W, R.slice_stride, R.ld) * sizeof(float2);
+      const size_t M2 = static_cast<size_t>(R.M) * R.M;
+      PT_BUF(device, R.obj, obj_bytes, "reconstruction object");
+      PT_BUF(device, R.grad, obj_bytes, "reconstruction gradient");
+      PT_BUF(device, R.probe, M2 * sizeof(float2), "reconstruction probe");
+      PT_BUF(device, R.pos, 2 * static_cast<size_t>(R.n) * sizeof(int32_t), "reconstruction positions");
+      PT_BUF(device, R.meas, static_cast<size_t>(R.n) * M2 * sizeof(float), "reconstruction measurements");
+    }
   }
   if (total_items >= (int64_t(1) << 30)) return fail(PTYCHO_E_CAPACITY, "too many positions");
   ptycho_batch* b = new ptycho_batch();

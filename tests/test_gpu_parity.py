@@ -218,6 +218,37 @@ def test_degenerate_inputs(torch_cuda):
         assert rel_l2(G.cpu().numpy(), G_ref) <= TOL_G
 
 
+def test_c_abi_refuses_host_memory_and_overruns(torch_cuda):
+    """The C ABI checks the caller's buffers on the host before enqueuing anything: a pageable
+    host pointer (E_ARG) and a position count that runs past the positions' allocation (E_SHAPE)
+    are refused, and the context stays usable."""
+    import ctypes
+    import paper_2205_06327_amd as pt
+    import torch
+    from paper_2205_06327_amd import _binding as B
+    spec = ps.with_overrides(ps.workload("2d-256-m64"), W=128, ny=2, nx=2, step=16)
+    say("C ABI: host pointer and overrun refused before launch")
+    d = problem(spec)
+    t = to_dev(d)
+    n_big = 300_000  # 2.4 MB of positions: past the 2 MB block holding the 4-position tensor
+    ctx = context(spec, n_big)
+    L = pt.lib()
+    S, H, W, ss, ld = B._obj_geometry(t["obj"])
+    host_out = np.zeros((4, 64, 64), dtype=np.float32)
+    vp = ctypes.c_void_p
+    rc = L.ptycho_forward(ctx.handle, vp(t["obj"].data_ptr()), H, W, ss, ld, vp(t["probe"].data_ptr()),
+                          vp(t["pos"].data_ptr()), 4, vp(host_out.ctypes.data))
+    assert B.ERRORS.get(rc) == "PTYCHO_E_ARG" and "device-accessible" in L.ptycho_last_error().decode()
+    out = torch.empty((4, 64, 64), dtype=torch.float32, device="cuda:0")
+    rc = L.ptycho_forward(ctx.handle, vp(t["obj"].data_ptr()), H, W, ss, ld, vp(t["probe"].data_ptr()),
+                          vp(t["pos"].data_ptr()), n_big, vp(out.data_ptr()))
+    assert B.ERRORS.get(rc) == "PTYCHO_E_SHAPE" and "positions" in L.ptycho_last_error().decode()
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    I = pt.ptycho_forward(ctx, t["obj"], t["probe"], t["pos"])
+    assert rel_l2(I.cpu().numpy(), oracle.forward(d["obj_eval"], d["probe"], d["pos"], d["H"])) <= TOL_I
+
+
 def test_checkpointed_wave_recomputation(torch_cuda):
     """Keeping only every k-th incident wave and recomputing the others in the adjoint sweep
     gives the same losses (the forward sweep is unchanged) and the same gradient up to the
