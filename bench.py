@@ -198,7 +198,7 @@ def run_batch(args, cores):
     log(f"inputs ready in {time.time() - t0:.1f} s: {total_pos} positions")
     iters = max(args.steps, 1)
     b = Batch(recons, history_rows=iters + args.warmup + 8)
-    tuned = tune(b, reps=2, cache_path=None)
+    tuned = tune(b, reps=10, cache_path=None)
     log(f"autotuner: {tuned}")
     start = [r.obj.clone() for r in recons]
     torch.cuda.synchronize()

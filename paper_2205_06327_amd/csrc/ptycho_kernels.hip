@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
     jb.gslice = R.slice_stride;
     jb.gscale = 2.0f;
     jb.ck = 1;
-    const double f = run_position<G, kModeLossGrad>(jb, sh, twb, hy, ws, L);
+    const double f = run_position<G, kModeLossGrad, G::M == 128>(jb, sh, twb, hy, ws, L);
     if (L.tid == 0) a.item_loss[item] = f;
   }
 }
