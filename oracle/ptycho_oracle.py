@@ -66,6 +66,10 @@ __all__ = [
     "tile_gradient",
     "stitch_tile_gradients",
     "gd_step_size",
+    "shift_probe",
+    "split_subpixel",
+    "forward_subpixel",
+    "loss_and_gradient_subpixel",
     "transmission_from_potential",
     "potential_gradient",
     "neighbour_add",
@@ -437,3 +441,59 @@ def gd_step_size(probe: np.ndarray, pos: np.ndarray, Hobj: int, Wobj: int, S: in
 
 def gd_step(obj: np.ndarray, grad: np.ndarray, alpha: float) -> np.ndarray:
     return obj - alpha * grad
+
+
+# ---------------------------------------------------------------------------
+# Sub-pixel positions (a variant of the probe function p_i of Section II-B:
+# the probe translated to the i-th location, here by a fraction of a pixel).
+# Reading: a position (y, x) is split into the integer window corner
+# (floor y, floor x) and the fraction d = (y - floor y, x - floor x) in
+# [0, 1)^2; the probe at the position is the probe translated by d with the
+# Fourier shift theorem on the periodic M x M window grid,
+#   P_d(r) = F^-1[ F(P)(q) exp(-2 pi i (q_y d_y + q_x d_x) / M) ](r),
+# q = fftfreq(M) * M (integer frequencies, -M/2 at the Nyquist bin).  Everything
+# after the probe is the integer-position model with P replaced by P_d.
+# ---------------------------------------------------------------------------
+def shift_probe(probe: np.ndarray, dy: float, dx: float) -> np.ndarray:
+    """The probe translated by (dy, dx) pixels (any real values), complex128 [M, M]."""
+    M = probe.shape[0]
+    q = np.fft.fftfreq(M) * M
+    ramp = np.exp(-2j * np.pi * (q[:, None] * dy + q[None, :] * dx) / M)
+    return np.fft.ifft2(np.fft.fft2(np.asarray(probe, dtype=np.complex128)) * ramp)
+
+
+def split_subpixel(pos: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Real-valued positions [n, 2] -> (integer window corners int32 [n, 2], fractions float64 [n, 2])."""
+    pos = np.asarray(pos, dtype=np.float64)
+    corner = np.floor(pos)
+    return corner.astype(np.int32), pos - corner
+
+
+def forward_subpixel(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, H: np.ndarray) -> np.ndarray:
+    """Intensities for real-valued positions, float64 [n, M, M]."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    corner, frac = split_subpixel(pos)
+    M = probe.shape[0]
+    out = np.empty((len(corner), M, M), dtype=np.float64)
+    for i in range(len(corner)):
+        _, far = exit_waves(obj, shift_probe(probe, *frac[i]), int(corner[i, 0]), int(corner[i, 1]), H)
+        out[i] = np.abs(far) ** 2
+    return out
+
+
+def loss_and_gradient_subpixel(obj: np.ndarray, probe: np.ndarray, pos: np.ndarray, meas: np.ndarray,
+                               H: np.ndarray) -> Tuple[float, np.ndarray, np.ndarray]:
+    """F(V), per-position f_i and dF/dt for real-valued positions (the shifted probe per position)."""
+    obj = np.asarray(obj, dtype=np.complex128)
+    corner, frac = split_subpixel(pos)
+    M = probe.shape[0]
+    grad = np.zeros_like(obj)
+    per_pos = np.empty(len(corner), dtype=np.float64)
+    total = 0.0
+    for i in range(len(corner)):
+        y0, x0 = int(corner[i, 0]), int(corner[i, 1])
+        f_i, patches = position_loss_and_patch_gradients(obj, shift_probe(probe, *frac[i]), y0, x0, meas[i], H)
+        per_pos[i] = f_i
+        total += f_i
+        grad[:, y0:y0 + M, x0:x0 + M] += patches
+    return total, per_pos, grad

@@ -489,3 +489,76 @@ def test_potential_gradient_by_central_differences():
         Fm = oracle.loss_and_gradient(oracle.transmission_from_potential(Vm, sigma), d["probe"], d["pos"], meas, H)[0]
         fd = (Fp - Fm) / (2 * h)
         assert abs(fd - gV[s_, y, x]) <= 1e-6 * max(1.0, abs(fd)) + 1e-7 * np.abs(gV).max()
+
+
+# --- sub-pixel positions (probe translated by a fraction of a pixel) --------
+def test_shift_probe_integer_shift_is_a_cyclic_roll():
+    rng = np.random.default_rng(41)
+    P = rand_complex(rng, (16, 16))
+    for dy, dx in [(2, -3), (0, 5), (-7, 0), (15, 1)]:
+        np.testing.assert_allclose(oracle.shift_probe(P, dy, dx), np.roll(P, (dy, dx), axis=(0, 1)),
+                                   rtol=0, atol=1e-12)
+
+
+def test_shift_probe_single_fourier_mode_closed_form():
+    """A single Fourier mode exp(2 pi i f.r / M) translated by any real d is exp(2 pi i f.(r - d) / M):
+    pins the sign of the ramp and the integer-frequency convention (evaluated by explicit DFT sums
+    as well as by the oracle)."""
+    M = 16
+    r = np.arange(M)
+    for fy, fx in [(1, 0), (-3, 2), (7, -7), (0, -1)]:
+        P = np.exp(2j * np.pi * (fy * r[:, None] + fx * r[None, :]) / M)
+        for dy, dx in [(0.25, 0.0), (0.5, 0.75), (-0.3, 0.9), (1.5, -2.25)]:
+            want = np.exp(2j * np.pi * (fy * (r[:, None] - dy) + fx * (r[None, :] - dx)) / M)
+            np.testing.assert_allclose(oracle.shift_probe(P, dy, dx), want, rtol=0, atol=1e-12)
+            q = np.where(r < M // 2, r, r - M)  # integer frequencies, -M/2 at the Nyquist bin
+            ramp = np.exp(-2j * np.pi * (q[:, None] * dy + q[None, :] * dx) / M)
+            np.testing.assert_allclose(bf_idft2(bf_dft2(P) * ramp), want, rtol=0, atol=1e-11)
+
+
+def test_shift_probe_composes_and_is_unitary():
+    rng = np.random.default_rng(43)
+    P = rand_complex(rng, (32, 32))
+    a = oracle.shift_probe(oracle.shift_probe(P, 0.3, -0.45), 0.5, 0.2)
+    np.testing.assert_allclose(a, oracle.shift_probe(P, 0.8, -0.25), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(oracle.shift_probe(oracle.shift_probe(P, 0.37, 0.61), -0.37, -0.61), P,
+                               rtol=0, atol=1e-12)
+    assert abs(np.linalg.norm(oracle.shift_probe(P, 0.37, 0.61)) - np.linalg.norm(P)) <= 1e-12 * np.linalg.norm(P)
+
+
+def test_subpixel_model_reduces_to_the_integer_model():
+    rng, obj, probe, pos = tiny_problem(seed=44, M=8, S=3)
+    H = oracle.fresnel_propagator(8, LAM, DZ, PIX)
+    meas = _meas_for(obj, probe, pos, H, rng)
+    posf = pos.astype(np.float64)
+    corner, frac = oracle.split_subpixel(posf + 0.0)
+    assert np.array_equal(corner, pos) and not frac.any()
+    np.testing.assert_allclose(oracle.forward_subpixel(obj, probe, posf, H), oracle.forward(obj, probe, pos, H),
+                               rtol=0, atol=1e-12)
+    L0, _, G0 = oracle.loss_and_gradient(obj, probe, pos, meas, H)
+    L1, _, G1 = oracle.loss_and_gradient_subpixel(obj, probe, posf, meas, H)
+    assert abs(L1 - L0) <= 1e-12 * L0  # the zero shift is the identity up to FFT rounding
+    np.testing.assert_allclose(G1, G0, rtol=0, atol=1e-12 * np.abs(G0).max())
+    # a fraction goes to the probe, the integer part to the window corner
+    corner, frac = oracle.split_subpixel(np.array([[2.25, 3.5], [0.0, 1.75]]))
+    assert corner.tolist() == [[2, 3], [0, 1]] and np.allclose(frac, [[0.25, 0.5], [0.0, 0.75]])
+
+
+def test_subpixel_gradient_by_central_differences():
+    rng, obj, probe, pos = tiny_problem(seed=45, M=8, S=2)
+    H = oracle.fresnel_propagator(8, LAM, DZ, PIX)
+    posf = pos.astype(np.float64) + rng.uniform(0.0, 1.0, pos.shape)
+    posf = np.minimum(posf, obj.shape[1] - 8)  # windows stay inside the object
+    meas = oracle.forward_subpixel(obj, probe, posf, H) * rng.uniform(0.5, 1.5, (len(pos), 8, 8))
+    _, _, G = oracle.loss_and_gradient_subpixel(obj, probe, posf, meas, H)
+    h = 1e-6
+    fd = np.zeros_like(G)
+    for idx in np.ndindex(obj.shape):
+        for unit in (1.0, 1j):
+            op, om = obj.copy(), obj.copy()
+            op[idx] += h * unit
+            om[idx] -= h * unit
+            d = (oracle.loss_and_gradient_subpixel(op, probe, posf, meas, H)[0]
+                 - oracle.loss_and_gradient_subpixel(om, probe, posf, meas, H)[0]) / (2 * h)
+            fd[idx] += d * unit
+    np.testing.assert_allclose(G, fd, rtol=0, atol=2e-6 * np.abs(G).max())
