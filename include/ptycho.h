@@ -218,6 +218,38 @@ int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t 
                            void* probe_grad, uint32_t flags, const double* grad_scale);
 
 /*
+ * Sub-pixel positions (the probe function p_i of Section II-B translated to
+ * the i-th location by a fraction of a pixel).  A position (y, x) splits into
+ * the integer window corner (floor y, floor x), passed in pos as usual, and
+ * the fraction d = (y - floor y, x - floor x); the probe at the position is
+ * P_d = F^-1[F(P) exp(-2 pi i (q_y d_y + q_x d_x)/M)] on the periodic M x M
+ * window grid, q the integer frequencies (-M/2 at the Nyquist bin), i.e. P
+ * translated by d.  Everything after the probe is the integer-position model.
+ *
+ * ptycho_shift_probes: out[i] = P translated by shifts[i] = (d_y, d_x), for
+ * i < n.  probe: device complex64 [M][M]; shifts: device float32 [n][2] (any
+ * finite values; the fraction is the intended use); out: device complex64
+ * [n][M][M], overwritten, must not overlap the probe (E_ARG).  Non-finite
+ * shifts give non-finite probes (no other effect).
+ *
+ * ptycho_forward_stack / ptycho_loss_grad_stack: ptycho_forward and
+ * ptycho_loss_grad with one probe per position: position i uses
+ * probes + i*probe_stride (complex64 [M][M] each), probe_stride >= M*M
+ * (else E_SHAPE).  With the probes from ptycho_shift_probes and the integer
+ * corners in pos they compute the sub-pixel model.  The object gradient is
+ * as in ptycho_loss_grad; the probe gradient is not offered for stacks.
+ */
+int ptycho_shift_probes(ptycho_ctx* ctx, const void* probe, const float* shifts, int32_t n, void* out);
+int ptycho_forward_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                         int32_t ld, const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n,
+                         float* intens);
+int ptycho_loss_grad_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                           int32_t ld, const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n,
+                           const float* meas, double* loss, double* loss_per_pos, void* grad,
+                           int64_t grad_slice_stride, int32_t grad_ld, uint32_t flags,
+                           const double* grad_scale);
+
+/*
  * ptycho_loss: the amplitude cost F (Eq. 1) alone -- the forward sweep and
  * the detector-plane residual, without the adjoint.  loss / loss_per_pos /
  * flags as for ptycho_loss_grad.

@@ -9,6 +9,8 @@ from ._binding import (  # noqa: F401
     bin_positions,
     lib,
     ptycho_forward,
+    ptycho_shift_probes,
+    split_positions,
     ptycho_loss,
     ptycho_loss_grad,
     ptycho_tile_accumulate,

@@ -46,7 +46,8 @@ EXPORTED = (
     "ptycho_batch_replay", "ptycho_batch_sync", "ptycho_batch_history", "ptycho_batch_reset_history",
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
-    "ptycho_copy_box", "ptycho_tiles_grad",
+    "ptycho_copy_box", "ptycho_tiles_grad", "ptycho_shift_probes", "ptycho_forward_stack",
+    "ptycho_loss_grad_stack",
 )
 
 
@@ -95,6 +96,11 @@ def lib() -> ctypes.CDLL:
             "ptycho_profile_enable": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_zero_gradient": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32]),
             "ptycho_set_checkpoint": (ctypes.c_int, [c_vp, c_i32]),
+            "ptycho_shift_probes": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i32, c_vp]),
+            "ptycho_forward_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp, c_i32,
+                                                    c_vp]),
+            "ptycho_loss_grad_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp,
+                                                      c_i32, c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_u32, c_vp]),
             "ptycho_copy_box": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32]),
             "ptycho_tiles_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, ctypes.POINTER(TileDesc),
                                                  c_i32, c_i32, c_vp, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_u32]),
@@ -199,6 +205,16 @@ def _need_pos(pos) -> int:
     return int(pos.shape[0])
 
 
+def _need_probe(probe, M: int, n: int) -> int:
+    """One probe complex64 [M, M] (returns stride 0) or one per position [n, M, M] (returns M*M)."""
+    torch = _torch()
+    if isinstance(probe, torch.Tensor) and probe.dim() == 3:
+        _need(probe, torch.complex64, (n, M, M), "probe stack")
+        return M * M
+    _need(probe, torch.complex64, (M, M), "probe")
+    return 0
+
+
 def _need(t, dtype, shape=None, name="tensor"):
     torch = _torch()
     _on_device(t, name)
@@ -269,21 +285,27 @@ class Context:
 
 
 def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
-    """I_i = |G(p_i, V)|^2 for every position; returns float32 [n, M, M]."""
+    """I_i = |G(p_i, V)|^2 for every position; returns float32 [n, M, M].
+
+    probe: complex64 [M, M], or [n, M, M] with one probe per position (ptycho_forward_stack, e.g. the
+    sub-pixel probes of ptycho_shift_probes)."""
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
     if S != ctx.S:
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
-    _need(probe, torch.complex64, (M, M), "probe")
-    _need_pos(pos)
-    n = pos.shape[0]
+    n = _need_pos(pos)
+    pstride = _need_probe(probe, M, n)
     if intens is None:
         intens = torch.empty((n, M, M), dtype=torch.float32, device=obj.device)
     _need(intens, torch.float32, (n, M, M), "intens")
     ctx._bind_stream()
-    _check(lib().ptycho_forward(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
-                                c_vp(pos.data_ptr()), n, c_vp(intens.data_ptr())))
+    if pstride:
+        _check(lib().ptycho_forward_stack(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                          pstride, c_vp(pos.data_ptr()), n, c_vp(intens.data_ptr())))
+    else:
+        _check(lib().ptycho_forward(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                    c_vp(pos.data_ptr()), n, c_vp(intens.data_ptr())))
     return intens
 
 
@@ -319,15 +341,18 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
     grad_scale: optional float64 [1] device tensor multiplying the gradient.
     probe_grad: optional complex64 [M, M] device tensor that receives dF/dP
     (ptycho_loss_grad_probe).
+    probe: complex64 [M, M], or [n, M, M] with one probe per position (ptycho_loss_grad_stack; no
+    probe gradient then).
     """
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
     if S != ctx.S:
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
-    _need(probe, torch.complex64, (M, M), "probe")
-    _need_pos(pos)
-    n = pos.shape[0]
+    n = _need_pos(pos)
+    pstride = _need_probe(probe, M, n)
+    if pstride and probe_grad is not None:
+        raise ValueError("the probe gradient needs one probe shared by all positions")
     _need(meas, torch.float32, (n, M, M), "meas")
     if grad is None:
         grad = torch.empty((S, H, W), dtype=torch.complex64, device=obj.device)
@@ -346,7 +371,12 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
         gs = c_vp(grad_scale.data_ptr())
     ctx._bind_stream()
     flags = PTYCHO_ACCUMULATE if accumulate else 0
-    if probe_grad is None:
+    if pstride:
+        _check(lib().ptycho_loss_grad_stack(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                            pstride, c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()),
+                                            c_vp(loss.data_ptr()), lpp, c_vp(grad.data_ptr()), grad.stride(0),
+                                            grad.stride(1), flags, gs))
+    elif probe_grad is None:
         _check(lib().ptycho_loss_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
                                       c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
                                       c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1), flags, gs))
@@ -357,6 +387,34 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
                                             lpp, c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
                                             c_vp(probe_grad.data_ptr()), flags, gs))
     return loss, grad
+
+
+def ptycho_shift_probes(ctx: Context, probe, shifts, out=None):
+    """The probe translated by shifts[i] = (dy, dx) pixels for every i (Fourier shift theorem on the
+    window grid); probe complex64 [M, M], shifts float32 [n, 2] on the device; returns [n, M, M]."""
+    torch = _torch()
+    M = ctx.M
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(shifts, torch.float32, None, "shifts")
+    if shifts.dim() != 2 or shifts.shape[1] != 2:
+        raise ValueError(f"shifts must have shape [n, 2], got {tuple(shifts.shape)}")
+    n = int(shifts.shape[0])
+    if out is None:
+        out = torch.empty((n, M, M), dtype=torch.complex64, device=probe.device)
+    _need(out, torch.complex64, (n, M, M), "out")
+    ctx._bind_stream()
+    _check(lib().ptycho_shift_probes(ctx.handle, c_vp(probe.data_ptr()), c_vp(shifts.data_ptr()), n,
+                                     c_vp(out.data_ptr())))
+    return out
+
+
+def split_positions(pos):
+    """Real-valued positions [n, 2] (host array) -> (integer window corners int32 [n, 2], fractions
+    float32 [n, 2] in [0, 1)), the split of a sub-pixel position into window and probe translation."""
+    import numpy as np
+    p = np.asarray(pos, dtype=np.float64).reshape(-1, 2)
+    corner = np.floor(p)
+    return corner.astype(np.int32), (p - corner).astype(np.float32)
 
 
 def ptycho_tile_grad(ctx: Context, obj_ext, box, tile, halo: int, H: int, W: int, probe, pos, meas,

@@ -153,11 +153,13 @@ size_t span_elems(int64_t S, int64_t h, int64_t w, int64_t slice_stride, int64_t
 
 // The object, probe, positions and (optional) patterns of a position call.
 int check_position_buffers(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
-                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas) {
+                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                           int64_t probe_stride = 0) {
   if (n == 0) return PTYCHO_OK;
   const size_t M2 = static_cast<size_t>(c->M) * c->M;
   PT_BUF(c->device, obj, span_elems(c->S, H, W, slice_stride, ld) * sizeof(float2), "object");
-  PT_BUF(c->device, probe, M2 * sizeof(float2), "probe");
+  PT_BUF(c->device, probe, (static_cast<size_t>(n - 1) * static_cast<size_t>(probe_stride) + M2) * sizeof(float2),
+         "probe");
   PT_BUF(c->device, pos, 2 * static_cast<size_t>(n) * sizeof(int32_t), "positions");
   PT_BUF(c->device, meas, static_cast<size_t>(n) * M2 * sizeof(float), "measurements");
   return PTYCHO_OK;
@@ -302,13 +304,24 @@ int ptycho_reserve(ptycho_ctx* ctx, int32_t max_positions) {
 
 int64_t ptycho_workspace_bytes(const ptycho_ctx* ctx) { return ctx ? ctx->bytes : 0; }
 
-int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
-                   const void* probe, const int32_t* pos, int32_t n, float* intens) {
+}  // extern "C"
+
+namespace {
+int check_probe_stride(const ptycho_ctx* c, int64_t probe_stride) {
+  if (probe_stride != 0 && probe_stride < static_cast<int64_t>(c->M) * c->M)
+    return fail(PTYCHO_E_SHAPE, "probe stride %lld: 0 (one probe) or >= M*M (one probe per position)",
+                static_cast<long long>(probe_stride));
+  return PTYCHO_OK;
+}
+
+int forward_impl(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                 const void* probe, int64_t probe_stride, const int32_t* pos, int32_t n, float* intens) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
+  if ((rc = check_probe_stride(ctx, probe_stride)) != PTYCHO_OK) return rc;
   if (n == 0) return PTYCHO_OK;
   if (!intens) return fail(PTYCHO_E_ARG, "null intensity output");
-  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, nullptr);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, nullptr, probe_stride);
   if (rc != PTYCHO_OK) return rc;
   PT_BUF(ctx->device, intens, static_cast<size_t>(n) * ctx->M * ctx->M * sizeof(float), "intensities");
   ptycho::KernelArgs a = base_args(ctx);
@@ -320,9 +333,24 @@ int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64
   a.bw = W;
   a.oob_flag = PTYCHO_STATUS_BOUNDS;
   a.probe = static_cast<const float2*>(probe);
+  a.probe_stride = probe_stride;
   a.pos = pos;
   a.intens = intens;
   return launch_fused_timed(ctx, a, ptycho::kModeIntensity);
+}
+}  // namespace
+
+extern "C" {
+
+int ptycho_forward(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                   const void* probe, const int32_t* pos, int32_t n, float* intens) {
+  return forward_impl(ctx, obj, H, W, slice_stride, ld, probe, 0, pos, n, intens);
+}
+
+int ptycho_forward_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                         const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n, float* intens) {
+  if (ctx && probe_stride == 0) return fail(PTYCHO_E_SHAPE, "a probe stack needs a probe stride >= M*M");
+  return forward_impl(ctx, obj, H, W, slice_stride, ld, probes, probe_stride, pos, n, intens);
 }
 
 int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
@@ -333,12 +361,18 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
                                 grad_slice_stride, grad_ld, nullptr, flags, grad_scale);
 }
 
-int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
-                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
-                           double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
-                           void* probe_grad, uint32_t flags, const double* grad_scale) {
+}  // extern "C"
+
+namespace {
+int loss_grad_impl(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                   const void* probe, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas,
+                   double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
+                   void* probe_grad, uint32_t flags, const double* grad_scale) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
+  if ((rc = check_probe_stride(ctx, probe_stride)) != PTYCHO_OK) return rc;
+  if (probe_grad && probe_stride != 0)
+    return fail(PTYCHO_E_UNSUPPORTED, "the probe gradient needs one probe shared by all positions");
   if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
   if (!loss || !grad) return fail(PTYCHO_E_ARG, "null loss or gradient");
   if (n > 0 && !meas) return fail(PTYCHO_E_ARG, "null measurements");
@@ -348,7 +382,7 @@ int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t 
   if (static_cast<int64_t>(grad_ld) * ctx->M >= (int64_t(1) << 31))
     return fail(PTYCHO_E_SHAPE, "gradient row stride too large");  // window row offsets are 32-bit
   if (grad == obj) return fail(PTYCHO_E_ARG, "gradient aliases the object");
-  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas, probe_stride);
   if (rc != PTYCHO_OK) return rc;
   PT_BUF(ctx->device, grad, span_elems(ctx->S, H, W, grad_slice_stride, grad_ld) * sizeof(float2), "gradient");
   PT_BUF(ctx->device, loss, sizeof(double), "loss");
@@ -371,9 +405,48 @@ int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t 
   a.gslice = grad_slice_stride;
   a.gld = grad_ld;
   a.grad_scale = grad_scale;
+  a.probe_stride = probe_stride;
   if (probe_grad && (probe_grad == grad || probe_grad == probe))
     return fail(PTYCHO_E_ARG, "probe gradient aliases the gradient or the probe");
   return run_loss_grad(ctx, a, H, W, loss, flags, static_cast<float2*>(probe_grad));
+}
+}  // namespace
+
+extern "C" {
+
+int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                           int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                           double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
+                           void* probe_grad, uint32_t flags, const double* grad_scale) {
+  return loss_grad_impl(ctx, obj, H, W, slice_stride, ld, probe, 0, pos, n, meas, loss, loss_per_pos, grad,
+                        grad_slice_stride, grad_ld, probe_grad, flags, grad_scale);
+}
+
+int ptycho_loss_grad_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                           const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas,
+                           double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride, int32_t grad_ld,
+                           uint32_t flags, const double* grad_scale) {
+  if (ctx && probe_stride == 0) return fail(PTYCHO_E_SHAPE, "a probe stack needs a probe stride >= M*M");
+  return loss_grad_impl(ctx, obj, H, W, slice_stride, ld, probes, probe_stride, pos, n, meas, loss, loss_per_pos,
+                        grad, grad_slice_stride, grad_ld, nullptr, flags, grad_scale);
+}
+
+int ptycho_shift_probes(ptycho_ctx* ctx, const void* probe, const float* shifts, int32_t n, void* out) {
+  if (!ctx) return fail(PTYCHO_E_ARG, "null context");
+  if (n < 0) return fail(PTYCHO_E_ARG, "negative count");
+  if (n == 0) return PTYCHO_OK;
+  if (!probe || !shifts || !out) return fail(PTYCHO_E_ARG, "null pointer argument");
+  const size_t M2 = static_cast<size_t>(ctx->M) * ctx->M;
+  const char* o = static_cast<const char*>(out);
+  const char* q = static_cast<const char*>(probe);
+  if (q < o + static_cast<size_t>(n) * M2 * sizeof(float2) && o < q + M2 * sizeof(float2))
+    return fail(PTYCHO_E_ARG, "the output aliases the probe");
+  PT_BUF(ctx->device, probe, M2 * sizeof(float2), "probe");
+  PT_BUF(ctx->device, shifts, 2 * static_cast<size_t>(n) * sizeof(float), "shifts");
+  PT_BUF(ctx->device, out, static_cast<size_t>(n) * M2 * sizeof(float2), "shifted probes");
+  PT_HIP(ptycho::launch_shift_probes(static_cast<const float2*>(probe), shifts, n, ctx->M, ctx->d_tw,
+                                     static_cast<float2*>(out), ctx->stream));
+  return PTYCHO_OK;
 }
 
 int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,

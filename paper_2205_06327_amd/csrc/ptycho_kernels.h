@@ -41,6 +41,7 @@ struct KernelArgs {
   int ty0, ty1, tx0, tx1;
   unsigned oob_flag;     // status bit raised for a window outside the box
   const float2* probe;
+  long long probe_stride;  // 0: one probe for all positions; else position p uses probe + p*probe_stride
   const int* pos;        // [n][2] global (y0, x0)
   const float2* tw;      // W_M^e, e in [0, M)
   const float2* h;       // separable propagator factor h[k], k in [0, M)
@@ -103,6 +104,8 @@ hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 hipError_t launch_zero_slices(float2* g, int S, int H, int W, long long gslice, long long gld, hipStream_t st);
 hipError_t launch_finalize_loss(const double* per, int n, double* loss, bool accumulate, hipStream_t st);
 hipError_t launch_clear_status(unsigned* status, hipStream_t st);
+hipError_t launch_shift_probes(const float2* probe, const float* shifts, int n, int M, const float2* tw, float2* out,
+                               hipStream_t st);
 hipError_t launch_zero_tiles(const TileDesc* tiles, int ntiles, int S, hipStream_t st);
 hipError_t launch_probe_reduce(const float2* part, int parts, int M, float2* probe_grad, bool accumulate,
                                hipStream_t st);

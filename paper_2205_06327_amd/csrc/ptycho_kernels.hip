@@ -556,6 +556,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
       continue;
     }
     jb.win = a.obj + static_cast<long long>(y0) * a.ld + x0;
+    jb.probe = a.probe + static_cast<long long>(p) * a.probe_stride;
     jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
     jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
     const double f = run_position<G, MODE, G::M == 128, true>(jb, sh, twb, hy, ws, L);
@@ -827,6 +828,62 @@ static hipError_t launch_fused_m(const KernelArgs& a, int mode, int grid, hipStr
     case kModeLossGradProbe: return launch_fused_t<M, kModeLossGradProbe>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Sub-pixel probe translation: out[p] = F^-1[F(probe) exp(-2 pi i (q_y d_y + q_x d_x)/M)]
+// with (d_y, d_x) = shifts[p] and integer frequencies q (-M/2 at the Nyquist bin),
+// one workgroup per position, on the same register/LDS transforms as the
+// fused kernels.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(Geo<M>::T) shift_probe_kernel(const float2* __restrict__ probe,
+                                                                const float* __restrict__ shifts, int n,
+                                                                const float2* __restrict__ tw,
+                                                                float2* __restrict__ out) {
+  using G = Geo<M>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  const Lanes<G> L;
+  const int p = static_cast<int>(blockIdx.x);
+  if (p >= n) return;
+  float2 twb[G::X1];
+  load_twb<G>(twb, tw, L.m2);
+  float2 v[G::R];
+  load_window<G>(v, probe, G::M, L);
+  dft2_a_to_c<G>(v, lds, twb, L);
+  const float dy = shifts[2 * p], dx = shifts[2 * p + 1];
+  const int qy = L.ky < M / 2 ? L.ky : L.ky - M;
+  const float inv_n = 1.0f / float(M * M);
+  sfor<G::CJ>([&](auto lc) {
+    sfor<G::X2>([&](auto jc) {
+      constexpr int jl = decltype(lc)::value, j2 = decltype(jc)::value;
+      const int kx = L.jh * G::CJ + jl + G::X1 * j2;
+      const int qx = kx < M / 2 ? kx : kx - M;
+      // phase -2 pi (qy dy + qx dx)/M, in units of pi, reduced to [-1, 1] before the sine/cosine
+      float t = -2.0f * (static_cast<float>(qy) * dy + static_cast<float>(qx) * dx) / float(M);
+      t -= 2.0f * rintf(0.5f * t);
+      float sn, cs;
+      sincospif(t, &sn, &cs);
+      float2& e = v[jl * G::X2 + j2];
+      e = cmul(e, make_float2(cs * inv_n, sn * inv_n));
+    });
+  });
+  idft2_c_to_a<G>(v, lds, twb, L);
+  float2* __restrict__ o = out + static_cast<long long>(p) * (M * M) + L.n2 * M + L.x;
+  sfor<G::R>([&](auto rc) { o[decltype(rc)::value * G::Y2 * M] = v[decltype(rc)::value]; });
+}
+
+hipError_t launch_shift_probes(const float2* probe, const float* shifts, int n, int M, const float2* tw, float2* out,
+                               hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (M == 128) {
+    hipLaunchKernelGGL((shift_probe_kernel<128>), dim3(n), dim3(Geo<128>::T), 0, st, probe, shifts, n, tw, out);
+  } else if (M == 64) {
+    hipLaunchKernelGGL((shift_probe_kernel<64>), dim3(n), dim3(Geo<64>::T), 0, st, probe, shifts, n, tw, out);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_fused(const KernelArgs& a, int mode, int grid, hipStream_t st) {
