@@ -333,6 +333,24 @@ def directional_passes(ctx: B.Context, plan: TileWalk, bufs) -> None:
             exchange(ty * tx_n + tx, ty * tx_n + tx - 1, replace=True)
 
 
+def neighbour_add(ctx: B.Context, plan: TileWalk, src, dst) -> None:
+    """Section IV's single exchange: dst[k] = src[k] plus, on the overlaps, the original gradients
+    src[j] of tile k's (up to) eight direct neighbours; src and dst are separate per-tile buffers on
+    the extended boxes.  It sums every contribution to tile k's box only when tiles two apart do
+    not overlap (tile >= 2 halo); the directional passes cover the general case."""
+    ty_n, tx_n = plan.tiles
+    for k, p in enumerate(plan.plans):
+        ty, tx = divmod(k, tx_n)
+        origin = (p.box[0], p.box[1])
+        B.ptycho_box_exchange(ctx, src[k], origin, dst[k], origin, replace=True)
+        for dy in (-1, 0, 1):
+            for dx in (-1, 0, 1):
+                if (dy, dx) == (0, 0) or not (0 <= ty + dy < ty_n and 0 <= tx + dx < tx_n):
+                    continue
+                q = plan.plans[(ty + dy) * tx_n + tx + dx]
+                B.ptycho_box_exchange(ctx, src[q.index], (q.box[0], q.box[1]), dst[k], origin, replace=False)
+
+
 def stitch_interiors(ctx: B.Context, plan: TileWalk, bufs, out) -> None:
     """out[:, tile] = interior of bufs[k] for every tile k (Alg. 1's final stitch)."""
     for k, p in enumerate(plan.plans):
@@ -407,6 +425,15 @@ class DecomposedTileWalk:
     def passes(self) -> None:
         """Vertical forward (add) and backward (replace), then horizontal forward and backward."""
         directional_passes(self.ctx, self.plan, self.bufs)
+
+    def neighbour_add(self):
+        """Section IV's direct exchange of the tile gradients in ``bufs`` into a second set of
+        buffers (allocated on first use), which it returns; ``bufs`` keep the tiles' own gradients."""
+        import torch
+        if getattr(self, "acc", None) is None:
+            self.acc = [torch.empty_like(b) for b in self.bufs]
+        neighbour_add(self.ctx, self.plan, self.bufs, self.acc)
+        return self.acc
 
     def pass_bytes(self) -> int:
         """HBM bytes the passes move: overlap x S x 8 B, read twice and written once per add, read and

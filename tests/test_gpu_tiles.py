@@ -188,6 +188,43 @@ def test_decomposed_walk_directional_passes(torch_cuda):
     assert rel_l2(stitched.cpu().numpy(), g_h) <= 1e-6
 
 
+@pytest.mark.parametrize("tiles", [(2, 2), (4, 4)])
+def test_direct_neighbour_add(torch_cuda, tiles):
+    """Section IV's single exchange on the GPU against the oracle's: with 2x2 tiles of 192 px
+    (>= 2 halo) every box then holds the undecomposed gradient; with 4x4 tiles of 96 px it misses
+    the tiles two apart, exactly as the oracle's exchange does."""
+    import torch
+    from paper_2205_06327_amd.tilewalk import DecomposedTileWalk, TileWalk
+    spec = ps.with_overrides(tiled_spec(), tiles=tiles)
+    say(f"direct neighbour add, {tiles[0]}x{tiles[1]} tiles, halo {spec.halo}")
+    d = problem(spec)
+    t = to_dev(d)
+    plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    ctx = context(spec, spec.n)
+    walk = DecomposedTileWalk(ctx, plan)
+    meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
+    walk.tile_gradients(t["obj"], t["probe"], meas_sorted)
+    acc = walk.neighbour_add()
+    assert walk.check() == 0
+    torch.cuda.synchronize()
+    ref_tiles = [oracle.tile_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"], spec.tiles,
+                                      spec.halo, *divmod(k, spec.tiles[1])) for k in range(len(plan.plans))]
+    ref = oracle.neighbour_add(ref_tiles, spec.tiles)
+    G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+    exact = min(p.tile[1] - p.tile[0] for p in plan.plans) >= 2 * spec.halo
+    for k, p in enumerate(plan.plans):
+        ey0, ex0, eh, ew = p.box
+        buf = acc[k].cpu().numpy()
+        assert rel_l2(buf, ref[k]["grad"]) <= 1e-4, k
+        assert rel_l2(walk.bufs[k].cpu().numpy(), ref_tiles[k]["grad"]) <= 1e-4, k  # sources untouched
+        if exact:
+            assert rel_l2(buf, G_ref[:, ey0:ey0 + eh, ex0:ex0 + ew]) <= 1e-4, k
+    if not exact:
+        worst = max(rel_l2(acc[k].cpu().numpy(), G_ref[:, p.box[0]:p.box[0] + p.box[2], p.box[1]:p.box[1] + p.box[3]])
+                    for k, p in enumerate(plan.plans))
+        assert worst > 1e-2
+
+
 @pytest.mark.parametrize("batch,T", [(4, 1), (4, 3)])
 def test_alg1_walk_matches_oracle(torch_cuda, batch, T):
     import torch
