@@ -232,8 +232,9 @@ int ptycho_loss_grad_probe(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t 
  * [n][M][M], overwritten, must not overlap the probe (E_ARG).  Non-finite
  * shifts give non-finite probes (no other effect).
  *
- * ptycho_forward_stack / ptycho_loss_grad_stack: ptycho_forward and
- * ptycho_loss_grad with one probe per position: position i uses
+ * ptycho_forward_stack / ptycho_loss_stack / ptycho_loss_grad_stack:
+ * ptycho_forward, ptycho_loss and ptycho_loss_grad with one probe per
+ * position: position i uses
  * probes + i*probe_stride (complex64 [M][M] each), probe_stride >= M*M
  * (else E_SHAPE).  With the probes from ptycho_shift_probes and the integer
  * corners in pos they compute the sub-pixel model.  The object gradient is
@@ -243,6 +244,9 @@ int ptycho_shift_probes(ptycho_ctx* ctx, const void* probe, const float* shifts,
 int ptycho_forward_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
                          int32_t ld, const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n,
                          float* intens);
+int ptycho_loss_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas,
+                      double* loss, double* loss_per_pos, uint32_t flags);
 int ptycho_loss_grad_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
                            int32_t ld, const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n,
                            const float* meas, double* loss, double* loss_per_pos, void* grad,

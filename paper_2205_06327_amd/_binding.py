@@ -47,7 +47,7 @@ EXPORTED = (
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
     "ptycho_copy_box", "ptycho_tiles_grad", "ptycho_shift_probes", "ptycho_forward_stack",
-    "ptycho_loss_grad_stack",
+    "ptycho_loss_grad_stack", "ptycho_loss_stack",
 )
 
 
@@ -99,6 +99,8 @@ def lib() -> ctypes.CDLL:
             "ptycho_shift_probes": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i32, c_vp]),
             "ptycho_forward_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp, c_i32,
                                                     c_vp]),
+            "ptycho_loss_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp, c_i32,
+                                                 c_vp, c_vp, c_vp, c_u32]),
             "ptycho_loss_grad_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp,
                                                       c_i32, c_vp, c_vp, c_vp, c_vp, c_i64, c_i32, c_u32, c_vp]),
             "ptycho_copy_box": (ctypes.c_int, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i64, c_i32, c_vp, c_i64, c_i32]),
@@ -310,15 +312,15 @@ def ptycho_forward(ctx: Context, obj, probe, pos, intens=None):
 
 
 def ptycho_loss(ctx: Context, obj, probe, pos, meas, loss=None, loss_per_pos=None, accumulate: bool = False):
-    """Amplitude cost F as a float64 [1] device tensor (forward sweep only)."""
+    """Amplitude cost F as a float64 [1] device tensor (forward sweep only); probe [M, M] or one per
+    position [n, M, M] (ptycho_loss_stack)."""
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
     if S != ctx.S:
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
-    _need(probe, torch.complex64, (M, M), "probe")
-    _need_pos(pos)
-    n = pos.shape[0]
+    n = _need_pos(pos)
+    pstride = _need_probe(probe, M, n)
     _need(meas, torch.float32, (n, M, M), "meas")
     if loss is None:
         loss = torch.zeros(1, dtype=torch.float64, device=obj.device)
@@ -328,9 +330,14 @@ def ptycho_loss(ctx: Context, obj, probe, pos, meas, loss=None, loss_per_pos=Non
         _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
         lpp = c_vp(loss_per_pos.data_ptr())
     ctx._bind_stream()
-    _check(lib().ptycho_loss(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
-                             c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
-                             PTYCHO_ACCUMULATE if accumulate else 0))
+    flags = PTYCHO_ACCUMULATE if accumulate else 0
+    if pstride:
+        _check(lib().ptycho_loss_stack(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                       pstride, c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()),
+                                       c_vp(loss.data_ptr()), lpp, flags))
+    else:
+        _check(lib().ptycho_loss(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, c_vp(probe.data_ptr()),
+                                 c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp, flags))
     return loss
 
 

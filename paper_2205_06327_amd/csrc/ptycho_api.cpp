@@ -449,16 +449,20 @@ int ptycho_shift_probes(ptycho_ctx* ctx, const void* probe, const float* shifts,
   return PTYCHO_OK;
 }
 
-int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
-                const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
-                double* loss_per_pos, uint32_t flags) {
+}  // extern "C"
+
+namespace {
+int loss_impl(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+              const void* probe, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas, double* loss,
+              double* loss_per_pos, uint32_t flags) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
+  if ((rc = check_probe_stride(ctx, probe_stride)) != PTYCHO_OK) return rc;
   if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
   if (!loss) return fail(PTYCHO_E_ARG, "null loss");
   if (n > 0 && !meas) return fail(PTYCHO_E_ARG, "null measurements");
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
-  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas, probe_stride);
   if (rc != PTYCHO_OK) return rc;
   PT_BUF(ctx->device, loss, sizeof(double), "loss");
   PT_BUF(ctx->device, loss_per_pos, static_cast<size_t>(n) * sizeof(double), "per-position losses");
@@ -471,6 +475,7 @@ int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t 
   a.bw = W;
   a.oob_flag = PTYCHO_STATUS_BOUNDS;
   a.probe = static_cast<const float2*>(probe);
+  a.probe_stride = probe_stride;
   a.pos = pos;
   a.meas = meas;
   a.loss_pos = loss_per_pos;
@@ -480,6 +485,22 @@ int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t 
   }
   PT_HIP(ptycho::launch_finalize_loss(ctx->d_loss, n, loss, (flags & PTYCHO_ACCUMULATE) != 0, ctx->stream));
   return PTYCHO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ptycho_loss(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                double* loss_per_pos, uint32_t flags) {
+  return loss_impl(ctx, obj, H, W, slice_stride, ld, probe, 0, pos, n, meas, loss, loss_per_pos, flags);
+}
+
+int ptycho_loss_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const void* probes, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas,
+                      double* loss, double* loss_per_pos, uint32_t flags) {
+  if (ctx && probe_stride == 0) return fail(PTYCHO_E_SHAPE, "a probe stack needs a probe stride >= M*M");
+  return loss_impl(ctx, obj, H, W, slice_stride, ld, probes, probe_stride, pos, n, meas, loss, loss_per_pos, flags);
 }
 
 int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int32_t ty, int32_t tx, int32_t halo,

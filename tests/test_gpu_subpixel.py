@@ -118,3 +118,30 @@ def test_probe_stack_validation(torch_cuda):
     assert B.ERRORS.get(rc) == "PTYCHO_E_SHAPE"
     I = pt.ptycho_forward(ctx, obj, stack, pos)
     assert rel_l2(I.cpu().numpy(), pt.ptycho_forward(ctx, obj, probe, pos).cpu().numpy()) == 0.0
+
+
+def test_subpixel_autograd(torch_cuda):
+    """amplitude_loss with one probe per position: the forward value from ptycho_loss_stack and the
+    object gradient from ptycho_loss_grad_stack, scaled by the upstream factor."""
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.autograd import amplitude_loss
+    spec = ps.with_overrides(ps.workload("ms8-1024-m128"), W=300, S=2, ny=1, nx=1, noise=True)
+    d = ps.build_inputs(spec)
+    rng = np.random.default_rng(23)
+    posf = rng.uniform(0.0, spec.W - spec.M - 1e-3, (9, 2))
+    say("sub-pixel positions through autograd, 9 positions")
+    Hp = oracle.fresnel_propagator(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
+    meas = ps.poisson_counts(oracle.forward_subpixel(d["obj_true"], d["probe"], posf, Hp), d["noise_seed"])
+    corner, frac = pt.split_positions(posf)
+    dev = "cuda:0"
+    ctx = context(spec, len(posf))
+    stack = pt.ptycho_shift_probes(ctx, torch.tensor(d["probe"], dtype=torch.complex64, device=dev),
+                                   torch.tensor(frac, device=dev))
+    obj = torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev).requires_grad_(True)
+    loss = amplitude_loss(ctx, obj, stack, torch.tensor(corner, device=dev), torch.tensor(meas, device=dev))
+    (0.25 * loss).backward()
+    assert ctx.check() == 0
+    L_ref, _, G_ref = oracle.loss_and_gradient_subpixel(d["obj_eval"], d["probe"], posf, meas, Hp)
+    assert abs(float(loss.item()) - L_ref) <= TOL_L * L_ref
+    assert rel_l2(obj.grad.cpu().numpy(), 0.25 * G_ref) <= TOL_G
