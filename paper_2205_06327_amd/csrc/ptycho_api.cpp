@@ -139,10 +139,15 @@ int check_buffer(int device, const void* p, size_t bytes, const char* what) {
   return PTYCHO_OK;
 }
 
-// Elements spanned by a [S][h][w] view with strides (slice_stride, ld), 0 when empty.
+// Elements spanned by a [S][h][w] view with strides (slice_stride, ld), 0 when empty.  Saturates at
+// kSpanCap (beyond any allocation, small enough that byte counts do not wrap), so absurd strides
+// fail the allocation check instead of wrapping around to a small span.
+constexpr size_t kSpanCap = size_t(1) << 56;
 size_t span_elems(int64_t S, int64_t h, int64_t w, int64_t slice_stride, int64_t ld) {
   if (S <= 0 || h <= 0 || w <= 0) return 0;
-  return static_cast<size_t>((S - 1) * (S > 1 ? slice_stride : 0) + (h - 1) * ld + w);
+  if (ld < 0 || (S > 1 && slice_stride < 0)) return kSpanCap;
+  const __int128 e = static_cast<__int128>(S - 1) * (S > 1 ? slice_stride : 0) + static_cast<__int128>(h - 1) * ld + w;
+  return e > static_cast<__int128>(kSpanCap) ? kSpanCap : static_cast<size_t>(e);
 }
 
 #define PT_BUF(dev, p, bytes, what)                               \
@@ -158,8 +163,7 @@ int check_position_buffers(const ptycho_ctx* c, const void* obj, int32_t H, int3
   if (n == 0) return PTYCHO_OK;
   const size_t M2 = static_cast<size_t>(c->M) * c->M;
   PT_BUF(c->device, obj, span_elems(c->S, H, W, slice_stride, ld) * sizeof(float2), "object");
-  PT_BUF(c->device, probe, (static_cast<size_t>(n - 1) * static_cast<size_t>(probe_stride) + M2) * sizeof(float2),
-         "probe");
+  PT_BUF(c->device, probe, span_elems(n, 1, static_cast<int64_t>(M2), probe_stride, 0) * sizeof(float2), "probe");
   PT_BUF(c->device, pos, 2 * static_cast<size_t>(n) * sizeof(int32_t), "positions");
   PT_BUF(c->device, meas, static_cast<size_t>(n) * M2 * sizeof(float), "measurements");
   return PTYCHO_OK;
