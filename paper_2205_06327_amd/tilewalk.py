@@ -224,7 +224,9 @@ class StreamingTileWalk:
     measurements and positions, one tile gradient and one gradient box.  For
     every tile the extended object box and the tile's measurements are copied
     in (pitched copies, ptycho_copy_box), the tile gradient is computed, the
-    global gradient's box is brought in, the tile gradient is added by the
+    global gradient's box is assembled on the device (zero, plus its overlaps
+    with the boxes already written back, the only parts of the global
+    gradient that are not zero yet), the tile gradient is added by the
     library's stitch kernel and the box is written back, so every addition
     happens on the GPU and the host only moves data.  Tiles alternate between
     two lanes (context + stream + buffers), so one tile's transfers overlap the
@@ -274,7 +276,6 @@ class StreamingTileWalk:
         S = self.ctx.S
         for s in self.streams:  # the previous step's write-backs into grad_host have landed
             s.synchronize()
-        grad_host.zero_()
         cur = torch.cuda.current_stream()
         start = torch.cuda.Event()
         start.record(cur)
@@ -282,8 +283,6 @@ class StreamingTileWalk:
             s.wait_event(start)
         written = None  # event after the previous tile's write-back of the global gradient
         for k, p in enumerate(self.plan.plans):
-            if p.hi == p.lo:
-                continue
             lane = k % len(self.ctxs)
             c, d, s = self.ctxs[lane], self.dev[lane], self.streams[lane]
             ey0, ex0, eh, ew = p.box
@@ -292,15 +291,28 @@ class StreamingTileWalk:
             tg = d["tile"].view(-1)[: S * eh * ew].view(S, eh, ew)
             gb = d["gbox"].view(-1)[: S * eh * ew].view(S, eh, ew)
             with torch.cuda.stream(s):
-                B.ptycho_copy_box(c, obj_host[:, ey0:ey0 + eh, ex0:ex0 + ew], ob)
-                d["meas"][:n_k].copy_(meas_host_sorted[p.lo:p.hi], non_blocking=True)
-                d["pos"][:n_k].copy_(self.pos_host[p.lo:p.hi], non_blocking=True)
-                B.ptycho_tile_grad(c, ob, p.box, p.tile, self.plan.halo, self.plan.H, self.plan.W, probe,
-                                   d["pos"][:n_k], d["meas"][:n_k], tile_grad=tg, loss=self.loss[k:k + 1])
+                if n_k > 0:
+                    B.ptycho_copy_box(c, obj_host[:, ey0:ey0 + eh, ex0:ex0 + ew], ob)
+                    d["meas"][:n_k].copy_(meas_host_sorted[p.lo:p.hi], non_blocking=True)
+                    d["pos"][:n_k].copy_(self.pos_host[p.lo:p.hi], non_blocking=True)
+                    B.ptycho_tile_grad(c, ob, p.box, p.tile, self.plan.halo, self.plan.H, self.plan.W, probe,
+                                       d["pos"][:n_k], d["meas"][:n_k], tile_grad=tg, loss=self.loss[k:k + 1])
+                else:
+                    self.loss[k:k + 1].zero_()
                 if written is not None:
                     s.wait_event(written)
-                B.ptycho_copy_box(c, grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew], gb)
-                B.ptycho_tile_accumulate(c, tg, (0, 0, eh, ew), gb)
+                # Only the boxes written back so far hold this step's global gradient (the boxes cover
+                # the object and every tile writes its box back, so nothing else is ever read): the
+                # box is cleared on the device and only its overlaps with those boxes come in.
+                B.ptycho_zero_gradient(c, gb)
+                for j in range(k):
+                    q = self.plan.plans[j]
+                    y0, x0 = max(ey0, q.box[0]), max(ex0, q.box[1])
+                    y1, x1 = min(ey0 + eh, q.box[0] + q.box[2]), min(ex0 + ew, q.box[1] + q.box[3])
+                    if y0 < y1 and x0 < x1:
+                        B.ptycho_copy_box(c, grad_host[:, y0:y1, x0:x1], gb[:, y0 - ey0:y1 - ey0, x0 - ex0:x1 - ex0])
+                if n_k > 0:
+                    B.ptycho_tile_accumulate(c, tg, (0, 0, eh, ew), gb)
                 B.ptycho_copy_box(c, gb, grad_host[:, ey0:ey0 + eh, ex0:ex0 + ew])
                 written = torch.cuda.Event()
                 written.record(s)
