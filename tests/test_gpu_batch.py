@@ -136,3 +136,35 @@ def test_autotuner_picks_a_valid_shape_and_caches(torch_cuda, tmp_path):
     second = tune(b2, reps=2, cache_path=cache)
     assert second["cached"] and second[64] == first[64] and second[128] == first[128]
     assert b2.grid(64) == min(first[64], sum(r.pos.shape[0] for r in recons if r.probe.shape[0] == 64))
+
+
+@pytest.mark.parametrize("M", [64, 128])
+def test_batch_one_window_size_with_an_empty_reconstruction(torch_cuda, M):
+    """A batch with a single window-size class (no side stream) and a reconstruction without
+    positions: its loss is 0, its gradient 0 and the update leaves it unchanged; the others match
+    the oracle."""
+    import torch
+    from paper_2205_06327_amd.batch import Batch, Recon
+    specs = [sp for sp in small_specs() if sp.M == M][:2]
+    say(f"batch of one window size (M={M}) plus an empty reconstruction")
+    probs, recons = build(specs, torch)
+    sp0, d0 = specs[0], probs[0]
+    dev = "cuda:0"
+    empty_obj = torch.tensor(d0["obj_eval"], dtype=torch.complex64, device=dev)
+    recons.append(Recon(empty_obj.clone(), torch.tensor(d0["probe"], dtype=torch.complex64, device=dev),
+                        torch.zeros((0, 2), dtype=torch.int32, device=dev),
+                        torch.zeros((0, M, M), dtype=torch.float32, device=dev),
+                        sp0.wavelength_A, sp0.dz_A, sp0.pixel_A, 1e-3))
+    b = Batch(recons, history_rows=4)
+    losses = torch.full((len(recons),), -1.0, dtype=torch.float64, device=dev)
+    b.loss_grad(losses)
+    b.sync()
+    L = losses.cpu().numpy()
+    assert L[-1] == 0.0 and float(recons[-1].grad.abs().max()) == 0.0
+    for sp, d, r, Lk in zip(specs, probs, recons, L):
+        L_ref, _, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])
+        assert abs(Lk - L_ref) <= 1e-5 * L_ref, sp.name
+        assert rel_l2(r.grad.cpu().numpy(), G_ref) <= 1e-4, sp.name
+    b.update()
+    b.sync()
+    assert torch.equal(recons[-1].obj, empty_obj)
