@@ -330,6 +330,15 @@ int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, in
                       const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
                       const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
                       double* loss_per_pos, uint32_t flags);
+/*
+ * ptycho_tiles_grad_stack: ptycho_tiles_grad with one probe per position
+ * (position i uses probes + i*probe_stride, probe_stride >= M*M, in the
+ * order of pos), e.g. the sub-pixel probes of ptycho_shift_probes.
+ */
+int ptycho_tiles_grad_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                            int32_t ld, const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo,
+                            const int32_t* tile_of_pos, const void* probes, int64_t probe_stride, const int32_t* pos,
+                            int32_t n, const float* meas, double* loss, double* loss_per_pos, uint32_t flags);
 
 /*
  * ptycho_tile_accumulate: the stitch step of the decomposition (Section III,

@@ -47,7 +47,7 @@ EXPORTED = (
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
     "ptycho_copy_box", "ptycho_tiles_grad", "ptycho_shift_probes", "ptycho_forward_stack",
-    "ptycho_loss_grad_stack", "ptycho_loss_stack",
+    "ptycho_loss_grad_stack", "ptycho_loss_stack", "ptycho_tiles_grad_stack",
 )
 
 
@@ -99,6 +99,9 @@ def lib() -> ctypes.CDLL:
             "ptycho_shift_probes": (ctypes.c_int, [c_vp, c_vp, c_vp, c_i32, c_vp]),
             "ptycho_forward_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp, c_i32,
                                                     c_vp]),
+            "ptycho_tiles_grad_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, ctypes.POINTER(TileDesc),
+                                                       c_i32, c_i32, c_vp, c_vp, c_i64, c_vp, c_i32, c_vp, c_vp, c_vp,
+                                                       c_u32]),
             "ptycho_loss_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp, c_i32,
                                                  c_vp, c_vp, c_vp, c_u32]),
             "ptycho_loss_grad_stack": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_i64, c_vp,
@@ -561,15 +564,15 @@ def ptycho_tiles_grad(ctx: Context, obj, tiles, halo: int, tile_of_pos, probe, p
                       loss_per_pos=None, accumulate: bool = False):
     """All tiles' gradients in one launch.  tiles: sequence of (tile (ty0, ty1, tx0, tx1),
     box (ey0, ex0, eh, ew), grad complex64 [S, eh, ew] contiguous); tile_of_pos int32 [n] and pos
-    int32 [n, 2] (global) on the device.  Returns the total loss (float64 [1])."""
+    int32 [n, 2] (global) on the device; probe [M, M] or one per position [n, M, M] in the order of
+    pos (ptycho_tiles_grad_stack).  Returns the total loss (float64 [1])."""
     torch = _torch()
     S, H, W, ss, ld = _obj_geometry(obj)
     if S != ctx.S:
         raise ValueError(f"object has {S} slices, context {ctx.S}")
     M = ctx.M
-    _need(probe, torch.complex64, (M, M), "probe")
-    _need_pos(pos)
-    n = pos.shape[0]
+    n = _need_pos(pos)
+    pstride = _need_probe(probe, M, n)
     _need(tile_of_pos, torch.int32, (n,), "tile_of_pos")
     _need(meas, torch.float32, (n, M, M), "meas")
     arr = (TileDesc * len(tiles))()
@@ -584,10 +587,16 @@ def ptycho_tiles_grad(ctx: Context, obj, tiles, halo: int, tile_of_pos, probe, p
         _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
         lpp = c_vp(loss_per_pos.data_ptr())
     ctx._bind_stream()
-    _check(lib().ptycho_tiles_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, arr, len(tiles), int(halo),
-                                   c_vp(tile_of_pos.data_ptr()), c_vp(probe.data_ptr()), c_vp(pos.data_ptr()), n,
-                                   c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp,
-                                   PTYCHO_ACCUMULATE if accumulate else 0))
+    flags = PTYCHO_ACCUMULATE if accumulate else 0
+    if pstride:
+        _check(lib().ptycho_tiles_grad_stack(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, arr, len(tiles),
+                                             int(halo), c_vp(tile_of_pos.data_ptr()), c_vp(probe.data_ptr()), pstride,
+                                             c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()),
+                                             lpp, flags))
+    else:
+        _check(lib().ptycho_tiles_grad(ctx.handle, c_vp(obj.data_ptr()), H, W, ss, ld, arr, len(tiles), int(halo),
+                                       c_vp(tile_of_pos.data_ptr()), c_vp(probe.data_ptr()), c_vp(pos.data_ptr()), n,
+                                       c_vp(meas.data_ptr()), c_vp(loss.data_ptr()), lpp, flags))
     return loss
 
 

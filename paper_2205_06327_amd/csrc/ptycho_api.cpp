@@ -578,19 +578,23 @@ int ptycho_tile_grad(ptycho_ctx* ctx, const void* obj_ext, int32_t ey0, int32_t 
   return run_loss_grad(ctx, a, eh, ew, loss, flags);
 }
 
-int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
-                      const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
-                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
-                      double* loss_per_pos, uint32_t flags) {
+}  // extern "C"
+
+namespace {
+int tiles_grad_impl(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                    const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
+                    const void* probe, int64_t probe_stride, const int32_t* pos, int32_t n, const float* meas,
+                    double* loss, double* loss_per_pos, uint32_t flags) {
   int rc = check_object_args(ctx, obj, H, W, slice_stride, ld, probe, pos, n);
   if (rc != PTYCHO_OK) return rc;
+  if ((rc = check_probe_stride(ctx, probe_stride)) != PTYCHO_OK) return rc;
   if (flags & ~PTYCHO_ACCUMULATE) return fail(PTYCHO_E_ARG, "unknown flags 0x%x", flags);
   if (!loss || !tiles || (n > 0 && (!meas || !tile_of_pos))) return fail(PTYCHO_E_ARG, "null pointer argument");
   if (ntiles < 1 || ntiles > ptycho::kMaxTiles) return fail(PTYCHO_E_ARG, "tile count %d outside [1, %d]", ntiles,
                                                             ptycho::kMaxTiles);
   if (halo < 0) return fail(PTYCHO_E_ARG, "negative halo");
   if (n > ctx->capacity) return fail(PTYCHO_E_CAPACITY, "%d positions exceed the reserved capacity %d", n, ctx->capacity);
-  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas);
+  rc = check_position_buffers(ctx, obj, H, W, slice_stride, ld, probe, pos, n, meas, probe_stride);
   if (rc != PTYCHO_OK) return rc;
   PT_BUF(ctx->device, tile_of_pos, static_cast<size_t>(n) * sizeof(int32_t), "tile indices");
   PT_BUF(ctx->device, loss, sizeof(double), "loss");
@@ -642,12 +646,33 @@ int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, in
   a.tiles = ctx->d_tiles;
   a.tile_of_pos = tile_of_pos;
   a.ntiles = ntiles;
+  a.probe_stride = probe_stride;
   if (n > 0) {
     rc = launch_fused_timed(ctx, a, ptycho::kModeLossGrad);
     if (rc != PTYCHO_OK) return rc;
   }
   PT_HIP(ptycho::launch_finalize_loss(ctx->d_loss, n, loss, acc, ctx->stream));
   return PTYCHO_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int ptycho_tiles_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride, int32_t ld,
+                      const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo, const int32_t* tile_of_pos,
+                      const void* probe, const int32_t* pos, int32_t n, const float* meas, double* loss,
+                      double* loss_per_pos, uint32_t flags) {
+  return tiles_grad_impl(ctx, obj, H, W, slice_stride, ld, tiles, ntiles, halo, tile_of_pos, probe, 0, pos, n, meas,
+                         loss, loss_per_pos, flags);
+}
+
+int ptycho_tiles_grad_stack(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                            int32_t ld, const ptycho_tile_desc* tiles, int32_t ntiles, int32_t halo,
+                            const int32_t* tile_of_pos, const void* probes, int64_t probe_stride, const int32_t* pos,
+                            int32_t n, const float* meas, double* loss, double* loss_per_pos, uint32_t flags) {
+  if (ctx && probe_stride == 0) return fail(PTYCHO_E_SHAPE, "a probe stack needs a probe stride >= M*M");
+  return tiles_grad_impl(ctx, obj, H, W, slice_stride, ld, tiles, ntiles, halo, tile_of_pos, probes, probe_stride,
+                         pos, n, meas, loss, loss_per_pos, flags);
 }
 
 int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, int32_t ex0, int32_t eh,

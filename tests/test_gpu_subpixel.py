@@ -145,3 +145,37 @@ def test_subpixel_autograd(torch_cuda):
     L_ref, _, G_ref = oracle.loss_and_gradient_subpixel(d["obj_eval"], d["probe"], posf, meas, Hp)
     assert abs(float(loss.item()) - L_ref) <= TOL_L * L_ref
     assert rel_l2(obj.grad.cpu().numpy(), 0.25 * G_ref) <= TOL_G
+
+
+def test_subpixel_all_tiles_launch(torch_cuda):
+    """The decomposition with sub-pixel positions: tiles binned by the integer window corners, one
+    shifted probe per position in tile order, all tiles in one launch (ptycho_tiles_grad_stack),
+    stitched, against the oracle's undecomposed sub-pixel gradient."""
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.tilewalk import AllTilesWalk, TileWalk
+    spec = ps.with_overrides(ps.workload("ms16-2048-m128-tiles4x4"), W=384, S=3, ny=8, nx=8, step=28,
+                             tiles=(2, 2), halo=64)
+    d = ps.build_inputs(spec)
+    rng = np.random.default_rng(29)
+    posf = d["pos"].astype(np.float64) + rng.uniform(0.0, 1.0, d["pos"].shape)
+    posf = np.minimum(posf, spec.W - spec.M)  # windows stay inside the object
+    say(f"sub-pixel positions through the all-tiles launch, {len(posf)} positions, 2x2 tiles")
+    Hp = oracle.fresnel_propagator(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
+    meas = ps.poisson_counts(oracle.forward_subpixel(d["obj_true"], d["probe"], posf, Hp), d["noise_seed"])
+    corner, frac = pt.split_positions(posf)
+    plan = TileWalk(corner, spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    dev = "cuda:0"
+    ctx = context(spec, len(posf))
+    stack = pt.ptycho_shift_probes(ctx, torch.tensor(d["probe"], dtype=torch.complex64, device=dev),
+                                   torch.tensor(frac[plan.order], device=dev))
+    meas_sorted = torch.tensor(meas[plan.order], device=dev)
+    obj = torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev)
+    grad = torch.empty_like(obj)
+    walk = AllTilesWalk(ctx, plan)
+    loss = float(walk.step(obj, stack, meas_sorted, grad).item())
+    assert walk.check() == 0
+    torch.cuda.synchronize()
+    L_ref, _, G_ref = oracle.loss_and_gradient_subpixel(d["obj_eval"], d["probe"], posf, meas, Hp)
+    assert abs(loss - L_ref) <= TOL_L * L_ref
+    assert rel_l2(grad.cpu().numpy(), G_ref) <= TOL_G
