@@ -249,6 +249,30 @@ def test_c_abi_refuses_host_memory_and_overruns(torch_cuda):
     assert rel_l2(I.cpu().numpy(), oracle.forward(d["obj_eval"], d["probe"], d["pos"], d["H"])) <= TOL_I
 
 
+def test_profile_events_count_launches_and_positions(torch_cuda):
+    """ptycho_profile_enable / ptycho_profile_read: HIP events around every fused launch on the
+    context stream; the read returns the summed time, the launch count and the positions, and resets."""
+    import torch
+    import paper_2205_06327_amd as pt
+    spec = ps.reduced(ps.workload("ms8-1024-m128"), W=256, ny=3, nx=3, S=2)
+    say("profiling events around the fused launches")
+    d = problem(spec)
+    t = to_dev(d)
+    ctx = context(spec, spec.n)
+    ctx.profile(True)
+    ctx.profile_read()
+    for _ in range(3):
+        pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"])
+    pt.ptycho_forward(ctx, t["obj"], t["probe"], t["pos"][:4].contiguous())
+    ms, launches, positions = ctx.profile_read()
+    assert launches == 4 and positions == 3 * spec.n + 4 and ms > 0.0
+    assert ctx.profile_read()[1] == 0  # the read resets the counts
+    ctx.profile(False)
+    pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"])
+    assert ctx.profile_read()[1] == 0
+    torch.cuda.synchronize()
+
+
 def test_checkpointed_wave_recomputation(torch_cuda):
     """Keeping only every k-th incident wave and recomputing the others in the adjoint sweep
     gives the same losses (the forward sweep is unchanged) and the same gradient up to the
