@@ -123,6 +123,20 @@ def test_streaming_walk_matches_resident(torch_cuda):
     torch.cuda.synchronize()
     ctx.check()
     assert rel_l2(gh.numpy(), grad.cpu().numpy()) <= 1e-6
+    # a tile without positions: its box still gets written (zero plus its neighbours' overlaps), so a
+    # host gradient full of garbage from before comes out right
+    keep = np.array([plan.plans[0].hi <= i for i in range(spec.n)])  # drop tile 0's positions
+    plan2 = TileWalk(plan.pos_sorted[keep], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    assert plan2.plans[0].hi == plan2.plans[0].lo
+    meas2 = meas_sorted[torch.tensor(np.nonzero(keep)[0], device="cuda:0")][torch.tensor(plan2.order, device="cuda:0")]
+    grad2 = torch.empty_like(t["obj"])
+    ResidentTileWalk(ctx, plan2).step(t["obj"], t["probe"], meas2.contiguous(), grad2)
+    gh.fill_(float("nan"))
+    StreamingTileWalk(plan2, ctx).step(t["obj"].cpu().pin_memory(), t["probe"], meas2.cpu().pin_memory(), gh)
+    torch.cuda.synchronize()
+    assert ctx.check() == 0
+    assert not torch.isnan(gh).any()
+    assert rel_l2(gh.numpy(), grad2.cpu().numpy()) <= 1e-6
 
 
 def test_lane_count_does_not_change_the_walk(torch_cuda):
