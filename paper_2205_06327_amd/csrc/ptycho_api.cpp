@@ -769,10 +769,13 @@ int ptycho_set_checkpoint(ptycho_ctx* ctx, int32_t interval) {
       hipError_t e = hipMalloc(&ws, new_elems * sizeof(float2));
       if (e != hipSuccess) return fail(PTYCHO_E_NOMEM, "wave store: %s", hipGetErrorString(e));
     }
-    if (ctx->d_ws) PT_HIP(hipFree(ctx->d_ws));
+    float2* old = ctx->d_ws;
     ctx->d_ws = ws;
     ctx->bytes += static_cast<int64_t>(new_elems) * static_cast<int64_t>(sizeof(float2)) -
                   static_cast<int64_t>(old_elems) * static_cast<int64_t>(sizeof(float2));
+    ctx->ck = interval;
+    if (old) PT_HIP(hipFree(old));  // the context already uses the new store
+    return PTYCHO_OK;
   }
   ctx->ck = interval;
   return PTYCHO_OK;
