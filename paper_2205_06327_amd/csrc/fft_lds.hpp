@@ -281,8 +281,25 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 
 // ---------------------------------------------------------------------------
 // LDS exchanges.  E1 holds element (k1, n2, x) at (k1*Y2 + n2)*RS1 + x.
-// E2 holds element (ky, j1, m2) at ky*RS2 + j1*X2 + (m2 ^ jh), jh = j1 / CJ
-// (the xor spreads the four jh lanes of a layout-C read over distinct banks).
+// E2 holds element (ky, j1, m2) in row Y2*(ky % Y1) + ky / Y1 at column
+// j1*X2 + (m2 ^ jh ^ 2*((ky % Y1) & 7)), jh = j1 / CJ.  The row order puts
+// the E2 data of layout-B thread (k1, m2) in the rows Y2*k1 .. Y2*k1 + 3 that
+// hold its E1 data, so each wave of layout B reads and writes the same 16
+// whole rows in both exchanges; the two xor terms spread the lanes of a
+// layout-C access (four jh, sixteen ky per wave) over distinct banks.
+//
+// Barriers.  A thread that writes an exchange only overwrites slots that it,
+// or its own wave, read last:
+//   * layout B: the E1 rows of a wave are its E2 rows (B -> C after A -> B,
+//     and B -> A after C -> B), and every value written depends on all
+//     values the thread read, so the writes follow the reads in the wave's
+//     instruction stream, and LDS operations of one wave complete in order;
+//   * layout C writes exactly the slots it read (C -> B after B -> C);
+//   * layout A writes exactly the slots it read (A -> B after B -> A).
+// So the barrier before such a write is not needed; the barrier between the
+// writes and the reads of an exchange always is.  The first write of a
+// transform keeps its barrier, since the buffer may have served another
+// purpose in between.
 // ---------------------------------------------------------------------------
 template <class G>
 __device__ __forceinline__ void e1_write_a(float2* lds, const float2 (&v)[G::R], int n2, int x) {
@@ -314,43 +331,58 @@ __device__ __forceinline__ void e1_write_b(float2* lds, const float2 (&b)[G::R],
     });
   });
 }
+// layout B: ky = k1 + Y1*k2, so the row is Y2*k1 + k2 and the bank term 2*(k1 & 7)
 template <class G>
 __device__ __forceinline__ void e2_write_b(float2* lds, const float2 (&b)[G::R], int k1, int m2) {
+  static_assert(G::RS1 == G::RS2, "E1 and E2 share rows");
+  const int u = m2 ^ (2 * (k1 & 7));
+  float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
       constexpr int k2 = decltype(kc)::value, j1 = decltype(jc)::value;
       constexpr int jh = j1 / G::CJ;
-      lds[(k1 + G::Y1 * k2) * G::RS2 + j1 * G::X2 + (m2 ^ jh)] = b[k2 * G::X1 + j1];
+      p[k2 * G::RS2 + j1 * G::X2 + (u ^ jh)] = b[k2 * G::X1 + j1];
     });
   });
 }
 template <class G>
 __device__ __forceinline__ void e2_read_b(const float2* lds, float2 (&b)[G::R], int k1, int m2) {
+  const int u = m2 ^ (2 * (k1 & 7));
+  const float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
       constexpr int k2 = decltype(kc)::value, j1 = decltype(jc)::value;
       constexpr int jh = j1 / G::CJ;
-      b[k2 * G::X1 + j1] = lds[(k1 + G::Y1 * k2) * G::RS2 + j1 * G::X2 + (m2 ^ jh)];
+      b[k2 * G::X1 + j1] = p[k2 * G::RS2 + j1 * G::X2 + (u ^ jh)];
     });
   });
 }
+// layout C: row Y2*(ky % Y1) + ky / Y1, bank term 2*((ky % Y1) & 7) folded into the lane xor
+template <class G>
+__device__ __forceinline__ const float2* e2_row_c(const float2* lds, int ky, int jh, int& t) {
+  const int kl = ky % G::Y1;
+  t = jh ^ (2 * (kl & 7));
+  return lds + (G::Y2 * kl + ky / G::Y1) * G::RS2 + jh * G::CJ * G::X2;
+}
 template <class G>
 __device__ __forceinline__ void e2_read_c(const float2* lds, float2 (&c)[G::R], int ky, int jh) {
-  const float2* p = lds + ky * G::RS2 + jh * G::CJ * G::X2;
+  int t;
+  const float2* p = e2_row_c<G>(lds, ky, jh, t);
   sfor<G::CJ>([&](auto lc) {
     sfor<G::X2>([&](auto mc) {
       constexpr int jl = decltype(lc)::value, m2 = decltype(mc)::value;
-      c[jl * G::X2 + m2] = p[jl * G::X2 + (m2 ^ jh)];
+      c[jl * G::X2 + m2] = p[jl * G::X2 + (m2 ^ t)];
     });
   });
 }
 template <class G>
 __device__ __forceinline__ void e2_write_c(float2* lds, const float2 (&c)[G::R], int ky, int jh) {
-  float2* p = lds + ky * G::RS2 + jh * G::CJ * G::X2;
+  int t;
+  float2* p = const_cast<float2*>(e2_row_c<G>(lds, ky, jh, t));
   sfor<G::CJ>([&](auto lc) {
     sfor<G::X2>([&](auto mc) {
       constexpr int jl = decltype(lc)::value, m2 = decltype(mc)::value;
-      p[jl * G::X2 + (m2 ^ jh)] = c[jl * G::X2 + m2];
+      p[jl * G::X2 + (m2 ^ t)] = c[jl * G::X2 + m2];
     });
   });
 }

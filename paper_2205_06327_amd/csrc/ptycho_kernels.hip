@@ -91,7 +91,6 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
   __syncthreads();
   e1_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_fwd<G>(v, twb);
-  __syncthreads();
   e2_write_b<G>(lds, v, L.k1, L.m2);
   __syncthreads();
   e2_read_c<G>(lds, v, L.ky, L.jh);
@@ -106,12 +105,10 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
     });
   });
   pass_c<G, true>(v);
-  __syncthreads();
   e2_write_c<G>(lds, v, L.ky, L.jh);
   __syncthreads();
   e2_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_inv<G>(v, twb);
-  __syncthreads();
   e1_write_b<G>(lds, v, L.k1, L.m2);
   __syncthreads();
   e1_read_a<G>(lds, v, L.n2, L.x);
@@ -129,7 +126,6 @@ __device__ __forceinline__ void dft2_a_to_c(float2 (&v)[G::R], float2* lds, cons
   __syncthreads();
   e1_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_fwd<G>(v, twb);
-  __syncthreads();
   e2_write_b<G>(lds, v, L.k1, L.m2);
   __syncthreads();
   e2_read_c<G>(lds, v, L.ky, L.jh);
@@ -147,7 +143,6 @@ __device__ __forceinline__ void idft2_c_to_a(float2 (&v)[G::R], float2* lds, con
   __syncthreads();
   e2_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_inv<G>(v, twb);
-  __syncthreads();
   e1_write_b<G>(lds, v, L.k1, L.m2);
   __syncthreads();
   e1_read_a<G>(lds, v, L.n2, L.x);
