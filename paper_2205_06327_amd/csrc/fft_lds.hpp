@@ -281,12 +281,13 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 
 // ---------------------------------------------------------------------------
 // LDS exchanges.  E1 holds element (k1, n2, x) at (k1*Y2 + n2)*RS1 + x.
-// E2 holds element (ky, j1, m2) in row Y2*(ky % Y1) + ky / Y1 at column
-// j1*X2 + (m2 ^ jh ^ 2*((ky % Y1) & 7)), jh = j1 / CJ.  The row order puts
+// E2 holds element (ky, j1, m2) in row Y2*k + ky / Y1, k = ky % Y1, at column
+// j1*X2 + (m2 ^ jh ^ e2_bank(k)), jh = j1 / CJ.  The row order puts
 // the E2 data of layout-B thread (k1, m2) in the rows Y2*k1 .. Y2*k1 + 3 that
 // hold its E1 data, so each wave of layout B reads and writes the same 16
 // whole rows in both exchanges; the two xor terms spread the lanes of a
-// layout-C access (four jh, sixteen ky per wave) over distinct banks.
+// layout-C access (four jh, sixteen ky per wave) over distinct banks, both
+// for 16 lanes served at a time over 32 banks and for 32 over 64.
 //
 // Barriers.  A thread that writes an exchange only overwrites slots that it,
 // or its own wave, read last:
@@ -331,11 +332,13 @@ __device__ __forceinline__ void e1_write_b(float2* lds, const float2 (&b)[G::R],
     });
   });
 }
-// layout B: ky = k1 + Y1*k2, so the row is Y2*k1 + k2 and the bank term 2*(k1 & 7)
+// bank term of E2 row group k: 4 * ((k mod 4) xor bit 2 of k), in column bits 2..3
+__device__ __forceinline__ int e2_bank(int k) { return 4 * ((k & 3) ^ ((k >> 2) & 1)); }
+// layout B: ky = k1 + Y1*k2, so the row is Y2*k1 + k2 and the bank term e2_bank(k1)
 template <class G>
 __device__ __forceinline__ void e2_write_b(float2* lds, const float2 (&b)[G::R], int k1, int m2) {
   static_assert(G::RS1 == G::RS2, "E1 and E2 share rows");
-  const int u = m2 ^ (2 * (k1 & 7));
+  const int u = m2 ^ e2_bank(k1);
   float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
@@ -347,7 +350,7 @@ __device__ __forceinline__ void e2_write_b(float2* lds, const float2 (&b)[G::R],
 }
 template <class G>
 __device__ __forceinline__ void e2_read_b(const float2* lds, float2 (&b)[G::R], int k1, int m2) {
-  const int u = m2 ^ (2 * (k1 & 7));
+  const int u = m2 ^ e2_bank(k1);
   const float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
@@ -357,11 +360,11 @@ __device__ __forceinline__ void e2_read_b(const float2* lds, float2 (&b)[G::R], 
     });
   });
 }
-// layout C: row Y2*(ky % Y1) + ky / Y1, bank term 2*((ky % Y1) & 7) folded into the lane xor
+// layout C: row Y2*(ky % Y1) + ky / Y1, bank term e2_bank(ky % Y1) folded into the lane xor
 template <class G>
 __device__ __forceinline__ const float2* e2_row_c(const float2* lds, int ky, int jh, int& t) {
   const int kl = ky % G::Y1;
-  t = jh ^ (2 * (kl & 7));
+  t = jh ^ e2_bank(kl);
   return lds + (G::Y2 * kl + ky / G::Y1) * G::RS2 + jh * G::CJ * G::X2;
 }
 template <class G>
