@@ -202,9 +202,9 @@ struct Geo {
   static constexpr int X1 = M / X2;
   static constexpr int CJ = X1 / Y2;       // j1 values per thread in layout C
   static constexpr int T = Y2 * M;         // threads per workgroup
-  static constexpr int PAD1 = 4;           // row padding of the A<->B exchange (complex)
+  static constexpr int PAD1 = 3;           // row padding of the exchanges (complex; odd, see below)
   static constexpr int RS1 = M + PAD1;
-  static constexpr int PAD2 = 4;           // row padding of the B<->C exchange (complex)
+  static constexpr int PAD2 = PAD1;        // the two exchanges share rows
   static constexpr int RS2 = M + PAD2;
   static constexpr int LDS_ELEMS = M * (RS1 > RS2 ? RS1 : RS2);
   static_assert(X1 % Y2 == 0, "layout C needs X1 divisible by 4");
@@ -281,13 +281,14 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 
 // ---------------------------------------------------------------------------
 // LDS exchanges.  E1 holds element (k1, n2, x) at (k1*Y2 + n2)*RS1 + x.
-// E2 holds element (ky, j1, m2) in row Y2*k + ky / Y1, k = ky % Y1, at column
-// j1*X2 + (m2 ^ jh ^ e2_bank(k)), jh = j1 / CJ.  The row order puts
-// the E2 data of layout-B thread (k1, m2) in the rows Y2*k1 .. Y2*k1 + 3 that
-// hold its E1 data, so each wave of layout B reads and writes the same 16
-// whole rows in both exchanges; the two xor terms spread the lanes of a
-// layout-C access (four jh, sixteen ky per wave) over distinct banks, both
-// for 16 lanes served at a time over 32 banks and for 32 over 64.
+// E2 holds element (ky, j1, m2) in row Y2*(ky % Y1) + ky / Y1 at column
+// j1*X2 + (m2 ^ jh), jh = j1 / CJ.  The row order puts the E2 data of
+// layout-B thread (k1, m2) in the rows Y2*k1 .. Y2*k1 + 3 that hold its E1
+// data, so each wave of layout B reads and writes the same 16 whole rows in
+// both exchanges.  Banks: the row stride is odd (M + 3 complex), so the four
+// consecutive ky of a 16-lane layout-C access, Y2 rows apart, start 8 banks
+// apart (of 32), and the xor with jh spreads its four jh lanes within those
+// 8; every other access runs along a row.
 //
 // Barriers.  A thread that writes an exchange only overwrites slots that it,
 // or its own wave, read last:
@@ -332,60 +333,52 @@ __device__ __forceinline__ void e1_write_b(float2* lds, const float2 (&b)[G::R],
     });
   });
 }
-// bank term of E2 row group k: 4 * ((k mod 4) xor bit 2 of k), in column bits 2..3
-__device__ __forceinline__ int e2_bank(int k) { return 4 * ((k & 3) ^ ((k >> 2) & 1)); }
-// layout B: ky = k1 + Y1*k2, so the row is Y2*k1 + k2 and the bank term e2_bank(k1)
+// layout B: ky = k1 + Y1*k2, so the row is Y2*k1 + k2
 template <class G>
 __device__ __forceinline__ void e2_write_b(float2* lds, const float2 (&b)[G::R], int k1, int m2) {
   static_assert(G::RS1 == G::RS2, "E1 and E2 share rows");
-  const int u = m2 ^ e2_bank(k1);
   float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
       constexpr int k2 = decltype(kc)::value, j1 = decltype(jc)::value;
       constexpr int jh = j1 / G::CJ;
-      p[k2 * G::RS2 + j1 * G::X2 + (u ^ jh)] = b[k2 * G::X1 + j1];
+      p[k2 * G::RS2 + j1 * G::X2 + (m2 ^ jh)] = b[k2 * G::X1 + j1];
     });
   });
 }
 template <class G>
 __device__ __forceinline__ void e2_read_b(const float2* lds, float2 (&b)[G::R], int k1, int m2) {
-  const int u = m2 ^ e2_bank(k1);
   const float2* p = lds + k1 * G::Y2 * G::RS2;
   sfor<G::Y2>([&](auto kc) {
     sfor<G::X1>([&](auto jc) {
       constexpr int k2 = decltype(kc)::value, j1 = decltype(jc)::value;
       constexpr int jh = j1 / G::CJ;
-      b[k2 * G::X1 + j1] = p[k2 * G::RS2 + j1 * G::X2 + (u ^ jh)];
+      b[k2 * G::X1 + j1] = p[k2 * G::RS2 + j1 * G::X2 + (m2 ^ jh)];
     });
   });
 }
-// layout C: row Y2*(ky % Y1) + ky / Y1, bank term e2_bank(ky % Y1) folded into the lane xor
+// layout C: row Y2*(ky % Y1) + ky / Y1
 template <class G>
-__device__ __forceinline__ const float2* e2_row_c(const float2* lds, int ky, int jh, int& t) {
-  const int kl = ky % G::Y1;
-  t = jh ^ e2_bank(kl);
-  return lds + (G::Y2 * kl + ky / G::Y1) * G::RS2 + jh * G::CJ * G::X2;
+__device__ __forceinline__ const float2* e2_row_c(const float2* lds, int ky, int jh) {
+  return lds + (G::Y2 * (ky % G::Y1) + ky / G::Y1) * G::RS2 + jh * G::CJ * G::X2;
 }
 template <class G>
 __device__ __forceinline__ void e2_read_c(const float2* lds, float2 (&c)[G::R], int ky, int jh) {
-  int t;
-  const float2* p = e2_row_c<G>(lds, ky, jh, t);
+  const float2* p = e2_row_c<G>(lds, ky, jh);
   sfor<G::CJ>([&](auto lc) {
     sfor<G::X2>([&](auto mc) {
       constexpr int jl = decltype(lc)::value, m2 = decltype(mc)::value;
-      c[jl * G::X2 + m2] = p[jl * G::X2 + (m2 ^ t)];
+      c[jl * G::X2 + m2] = p[jl * G::X2 + (m2 ^ jh)];
     });
   });
 }
 template <class G>
 __device__ __forceinline__ void e2_write_c(float2* lds, const float2 (&c)[G::R], int ky, int jh) {
-  int t;
-  float2* p = const_cast<float2*>(e2_row_c<G>(lds, ky, jh, t));
+  float2* p = const_cast<float2*>(e2_row_c<G>(lds, ky, jh));
   sfor<G::CJ>([&](auto lc) {
     sfor<G::X2>([&](auto mc) {
       constexpr int jl = decltype(lc)::value, m2 = decltype(mc)::value;
-      p[jl * G::X2 + (m2 ^ t)] = c[jl * G::X2 + m2];
+      p[jl * G::X2 + (m2 ^ jh)] = c[jl * G::X2 + m2];
     });
   });
 }

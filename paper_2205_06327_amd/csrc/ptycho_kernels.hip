@@ -486,8 +486,14 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   return f;
 }
 
+// Waves per SIMD the position kernels are compiled for: a 128-window workgroup
+// (8 waves, 136 KB of LDS) fills a CU alone; three 64-window workgroups (4
+// waves, 35 KB of LDS each) share one, which caps the registers at 168 per lane.
+template <int M>
+constexpr int kWavesPerSimd = M == 64 ? 3 : 2;
+
 template <int M, int MODE>
-__global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
+__global__ void __launch_bounds__(Geo<M>::T, kWavesPerSimd<M>) fused_kernel(KernelArgs a) {
   using G = Geo<M>;
   constexpr bool LOSS = MODE != kModeIntensity;
   __shared__ Shared<G> sh;
@@ -568,7 +574,7 @@ __global__ void __launch_bounds__(Geo<M>::T) fused_kernel(KernelArgs a) {
 // objects, slice counts and scans), one workgroup per CU walking the list.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(Geo<M>::T) batch_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(Geo<M>::T, kWavesPerSimd<M>) batch_kernel(BatchArgs a) {
   using G = Geo<M>;
   __shared__ Shared<G> sh;
   __shared__ int job;
