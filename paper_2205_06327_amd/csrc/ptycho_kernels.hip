@@ -81,12 +81,13 @@ struct Lanes {
 // the adjoint, hy already carrying the 1/M^2 of the inverse transform.
 template <class G, bool ADJ>
 __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const float2* hx_lds,
-                                          const float2 (&twb)[G::X1], float2 hy, const Lanes<G>& L) {
+                                          const float2 (&twb)[G::X1], float2 hy, const Lanes<G>& L,
+                                          bool own_reads_last = false) {
   const int z = opaque_zero();
   lds += z;
   hx_lds += z;
   pass_a_fwd<G>(v, L.n2);
-  __syncthreads();
+  if (!own_reads_last) __syncthreads();  // the buffer may have served another purpose
   e1_write_a<G>(lds, v, L.n2, L.x);
   __syncthreads();
   e1_read_b<G>(lds, v, L.k1, L.m2);
@@ -118,10 +119,10 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
 // Forward 2D DFT, layout A -> layout C.
 template <class G>
 __device__ __forceinline__ void dft2_a_to_c(float2 (&v)[G::R], float2* lds, const float2 (&twb)[G::X1],
-                                            const Lanes<G>& L) {
+                                            const Lanes<G>& L, bool own_reads_last = false) {
   lds += opaque_zero();
   pass_a_fwd<G>(v, L.n2);
-  __syncthreads();
+  if (!own_reads_last) __syncthreads();
   e1_write_a<G>(lds, v, L.n2, L.x);
   __syncthreads();
   e1_read_b<G>(lds, v, L.k1, L.m2);
@@ -354,10 +355,12 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
     sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
     if (s + 1 < S) {
       load_window<G>(t, jb.win + (s + 1) * jb.sstride, jb.ld, L);  // in flight during the propagation
-      propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
+      // after the first slice the buffer was last read by the previous propagation's layout-A reads,
+      // the slots each thread writes first
+      propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L, s > 0);
     }
   }
-  dft2_a_to_c<G>(v, sh.lds, twb, L);
+  dft2_a_to_c<G>(v, sh.lds, twb, L, S > 1);
 
   // ---- detector plane, layout C: element (ky, kx = jh*CJ + jl + X1*j2)
   const long long row = static_cast<long long>(L.ky) * G::M;
@@ -443,7 +446,8 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
     }
     __builtin_amdgcn_sched_barrier(0);
     if constexpr (LINES) {
-      __syncthreads();  // the last transform's LDS reads are done
+      // no barrier: the last LDS access before this was the layout-A read that ends every transform,
+      // of the slots each thread now writes
       e1_write_a<G>(sh.lds + opaque_zero(), g, L.n2, L.x);
       __syncthreads();
       scatter_add_lines<G>(jb.grad + s * jb.gslice, jb.gld, sh.lds, L);
