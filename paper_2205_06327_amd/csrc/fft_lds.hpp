@@ -300,8 +300,9 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 //   * layout A writes exactly the slots it read (A -> B after B -> A).
 // So the barrier before such a write is not needed; the barrier between the
 // writes and the reads of an exchange always is.  The first write of a
-// transform keeps its barrier, since the buffer may have served another
-// purpose in between.
+// transform (layout A) keeps its barrier unless its caller knows that the
+// last access to the buffer was the layout-A read ending the previous
+// transform; otherwise the buffer may have served another purpose since.
 // ---------------------------------------------------------------------------
 template <class G>
 __device__ __forceinline__ void e1_write_a(float2* lds, const float2 (&v)[G::R], int n2, int x) {
