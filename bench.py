@@ -27,7 +27,7 @@ if ROOT not in sys.path:
 
 METRIC = "probe-positions/s, forward+adjoint gradient, fused vs plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; packed FP32 is not used by this build.
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; the kernels are compiled without packed FP32 instructions.
 FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 FP32_PACKED_PEAK_TFLOPS = 157.3
 
@@ -324,7 +324,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         msg = ("this benchmark runs on one GPU only: the decomposed tile walk is measured on a single MI355X; "
-               "multi-GPU tile exchange is not part of this build")
+               "multi-GPU tile exchange is not implemented")
         print(msg, file=sys.stderr)
         sys.exit(2)
 
