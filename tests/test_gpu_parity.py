@@ -57,6 +57,11 @@ CASES = {
     "m64 S=3 ragged 13 positions": ps.with_overrides(ps.workload("2d-256-m64"), W=160, S=3, ny=13, nx=1, step=7,
                                                       strength=0.4, noise=True),
     "m128 S=16 3x3 positions": ps.reduced(ps.workload("ms16-2048-m128-tiles4x4"), W=192, ny=3, nx=3, S=16),
+    # two slices: one propagation, then the far-field transform right after it (no barrier between)
+    "m128 S=2 2x3 positions": ps.with_overrides(ps.workload("ms8-1024-m128"), W=200, S=2, ny=2, nx=3, step=17,
+                                                 noise=True),
+    "m64 S=2 ragged 7 positions": ps.with_overrides(ps.workload("2d-256-m64"), W=140, S=2, ny=7, nx=1, step=11,
+                                                     strength=0.4, noise=True),
 }
 
 
