@@ -224,7 +224,7 @@ __device__ __forceinline__ void scatter_add_lines(float2* __restrict__ gbase, lo
   const int e = lane & 31;
   const float* __restrict__ lf = reinterpret_cast<const float*>(lds + opaque_zero());
   const int gldz = static_cast<int>(gld) + opaque_zero();
-#pragma unroll 2
+#pragma unroll 1  // one row at a time: measured faster than 2 or 4 (fewer atomics in flight per wave)
   for (int k = 0; k < G::M / NW; ++k) {
     const int y = wave + NW * k;
     float* row = reinterpret_cast<float*>(gbase + static_cast<long long>(y) * gldz);
