@@ -510,7 +510,7 @@ def main():
             "max_rel_l2_tile_buffer_vs_undecomposed": worst,
             "all_tile_buffers_bytes": dwalk.device_bytes(),
         }
-        # Section IV's direct exchange with the eight neighbours (exact here: tiles >= 2 halo)
+        # Section III's direct exchange with the eight neighbours (exact here: tiles >= 2 halo)
         dwalk.tile_gradients(obj, probe, meas)
         acc = dwalk.neighbour_add()
         dwalk.check()

@@ -13,7 +13,7 @@
  *   Section III (tiles + halos): the image gradient and the probe locations
  *       are divided into tiles; each tile is extended by a halo that covers its
  *       probe windows; tile gradients of overlapping regions are added.
- *   Section V: with separately held tile buffers, directional forward (add)
+ *   Section IV: with separately held tile buffers, directional forward (add)
  *       and backward (replace) passes leave the summed gradient on every
  *       tile's box (ptycho_box_exchange); Alg. 1 updates each tile with its
  *       own and its accumulated gradients (ptycho_box_axpy).
@@ -354,11 +354,11 @@ int ptycho_tile_accumulate(ptycho_ctx* ctx, const void* tile_grad, int32_t ey0, 
 
 /*
  * ptycho_box_exchange: one exchange of the accumulation passes between two
- * tiles' separately held gradient buffers (Section V; the buffers stand for
+ * tiles' separately held gradient buffers (Section IV; the buffers stand for
  * the accumulated-gradient buffers that neighbouring devices exchange).  On
  * the overlap of the two boxes, in global pixel coordinates,
  *   PTYCHO_EXCHANGE_ADD:     dst += src   (the forward passes, and the
- *                                          neighbour add of Section IV)
+ *                                          neighbour add of Section III)
  *   PTYCHO_EXCHANGE_REPLACE: dst  = src   (the backward passes).
  * src holds the box with top-left (sy0, sx0) and size sh x sw:
  * element (s, y, x) of the box at src[s*s_slice_stride + y*s_ld + x]; dst

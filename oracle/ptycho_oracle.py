@@ -311,7 +311,7 @@ def _view(buf: Dict[str, object], region: Tuple[int, int, int, int]) -> np.ndarr
 
 
 def neighbour_add(tile_results: Sequence[Dict[str, object]], tiles: Tuple[int, int]) -> List[Dict[str, object]]:
-    """Section IV: every tile adds the gradients of its eight direct neighbours on
+    """Section III: every tile adds the gradients of its eight direct neighbours on
     their overlaps (a single exchange of the original tile gradients)."""
     ty_n, tx_n = tiles
     out = [{"box": r["box"], "grad": np.array(r["grad"], copy=True)} for r in tile_results]
@@ -331,7 +331,7 @@ def neighbour_add(tile_results: Sequence[Dict[str, object]], tiles: Tuple[int, i
 
 def directional_passes(tile_results: Sequence[Dict[str, object]], tiles: Tuple[int, int]
                        ) -> List[Dict[str, object]]:
-    """Section V: accumulated-gradient buffers start as copies of the tile
+    """Section IV: accumulated-gradient buffers start as copies of the tile
     gradients; then, in this order,
       vertical forward   -- down every tile column, the buffer of row r is added
                             into row r+1 on their overlap;

@@ -322,7 +322,7 @@ class StreamingTileWalk:
 
 
 def directional_passes(ctx: B.Context, plan: TileWalk, bufs) -> None:
-    """Section V's passes between per-tile buffers (bufs[k] holds tile k's extended box), enqueued
+    """Section IV's passes between per-tile buffers (bufs[k] holds tile k's extended box), enqueued
     on the caller's current stream: down every tile column add, up every column replace, along
     every tile row add, back along every row replace."""
     ty_n, tx_n = plan.tiles
@@ -346,7 +346,7 @@ def directional_passes(ctx: B.Context, plan: TileWalk, bufs) -> None:
 
 
 def neighbour_add(ctx: B.Context, plan: TileWalk, src, dst) -> None:
-    """Section IV's single exchange: dst[k] = src[k] plus, on the overlaps, the original gradients
+    """Section III's single exchange: dst[k] = src[k] plus, on the overlaps, the original gradients
     src[j] of tile k's (up to) eight direct neighbours; src and dst are separate per-tile buffers on
     the extended boxes.  It sums every contribution to tile k's box only when tiles two apart do
     not overlap (tile >= 2 halo); the directional passes cover the general case."""
@@ -373,7 +373,7 @@ def stitch_interiors(ctx: B.Context, plan: TileWalk, bufs, out) -> None:
 
 
 class DecomposedTileWalk:
-    """The decomposition's per-device data flow on one GPU (Section V, Alg. 1).
+    """The decomposition's per-device data flow on one GPU (Section IV, Alg. 1).
 
     Every tile keeps its own accumulated-gradient buffer on its extended box,
     as each device of the paper's mesh does.  ``step`` computes every tile's
@@ -439,7 +439,7 @@ class DecomposedTileWalk:
         directional_passes(self.ctx, self.plan, self.bufs)
 
     def neighbour_add(self):
-        """Section IV's direct exchange of the tile gradients in ``bufs`` into a second set of
+        """Section III's direct exchange of the tile gradients in ``bufs`` into a second set of
         buffers (allocated on first use), which it returns; ``bufs`` keep the tiles' own gradients."""
         import torch
         if getattr(self, "acc", None) is None:

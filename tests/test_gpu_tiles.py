@@ -204,7 +204,7 @@ def test_decomposed_walk_directional_passes(torch_cuda):
 
 @pytest.mark.parametrize("tiles", [(2, 2), (4, 4)])
 def test_direct_neighbour_add(torch_cuda, tiles):
-    """Section IV's single exchange on the GPU against the oracle's: with 2x2 tiles of 192 px
+    """Section III's single exchange on the GPU against the oracle's: with 2x2 tiles of 192 px
     (>= 2 halo) every box then holds the undecomposed gradient; with 4x4 tiles of 96 px it misses
     the tiles two apart, exactly as the oracle's exchange does."""
     import torch

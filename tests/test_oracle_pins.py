@@ -400,7 +400,7 @@ def test_directional_passes_leave_the_global_sum_on_every_box(W, tiles, halo):
     for b, a in zip(bufs, acc):
         ey0, ey1, ex0, ex1 = b["box"]
         np.testing.assert_allclose(a["grad"], total[:, ey0:ey1, ex0:ex1], rtol=0, atol=1e-12 * np.abs(total).max())
-    # the single direct-neighbour exchange of Section IV is exact only when no two
+    # the single direct-neighbour exchange of Section III is exact only when no two
     # non-adjacent tiles overlap (tile >= 2 * halo on both axes)
     nb = oracle.neighbour_add(bufs, tiles)
     exact = all(np.allclose(n["grad"], total[:, n["box"][0]:n["box"][1], n["box"][2]:n["box"][3]], rtol=0,
