@@ -41,8 +41,12 @@ special cases, translation and global-phase covariance, zero gradient at the
 truth, central finite differences, the adjoint dot-product identity, torch
 autograd on tiny grids, the decomposition sum, tile binning by brute force,
 the directional passes and the neighbour add against the summed tile
-gradients (exact only with tile >= 2 halo for the neighbour add), and
-monotone descent.  ``gd_step_size`` is a reading (the paper states no step
+gradients (exact only with tile >= 2 halo for the neighbour add), monotone
+descent, and the Alg. 1 schedule of ``alg1_tiles`` in closed form
+(tests/test_oracle_alg1.py: one batch per tile, and two batches with the
+passes after each batch or after both, for tiles at least and less than twice
+the halo, built from the global gradient, the tile gradients and the passes'
+exactness; planted schedule mistakes fail them).  ``gd_step_size`` is a reading (the paper states no step
 size): its descent property is tested, its value is not pinned ("parity
 unpinned" for the step length itself).
 """
