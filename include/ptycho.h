@@ -303,6 +303,27 @@ int ptycho_tile_box(int32_t H, int32_t W, int32_t tiles_y, int32_t tiles_x, int3
                     int32_t* ey1, int32_t* ex0, int32_t* ex1);
 
 /*
+ * ptycho_gd_step_size: step length alpha of the gradient-descent update
+ * t <- t - alpha * grad (Section II-B, last paragraph of the formulation; the
+ * tile updates of Alg. 1).  The paper states no step length; this library's
+ * reading is the inverse of a bound on the Gauss-Newton curvature of the
+ * amplitude cost over S unit-modulus slices:
+ *   alpha = 1 / (2 M^2 S max_r sum_i |P(r - r_i)|^2),
+ * the maximum over the object pixels r, the sum over the windows i covering r
+ * (P the probe translated to window i).
+ *   host_probe: HOST complex64 [M][M] (interleaved float pairs), M in [1, 4096]
+ *   host_pos:   HOST int32 [n][2] window corners (y0, x0), every window inside H x W
+ *   S:          slice count, >= 1
+ *   alpha_out:  HOST double, written on success only
+ * Errors: PTYCHO_E_ARG (a null pointer, n < 0, a bad size, or no object pixel
+ * with non-zero coverage -- n = 0 or a zero probe -- where the bound is
+ * infinite), PTYCHO_E_BOUNDS (a window leaves the object).  Host only: it uses
+ * an H x W host coverage map and touches no device.
+ */
+int ptycho_gd_step_size(const void* host_probe, int32_t M, const int32_t* host_pos, int32_t n, int32_t H,
+                        int32_t W, int32_t S, double* alpha_out);
+
+/*
  * ptycho_tiles_grad: the gradients of all tiles of a decomposition in one
  * persistent launch (Section III): every position adds its window's gradient
  * into the gradient buffer of the tile that owns it, on that tile's extended
@@ -429,16 +450,20 @@ typedef struct ptycho_batch ptycho_batch;
  * everything the batch needs (work list, per-item and per-reconstruction
  * losses, a loss history of history_rows iterations, the incident-wave store
  * of each window size).  The batch owns a stream of its own (default priority,
- * non-blocking); callers order their own work against it with
- * ptycho_batch_sync.  The arrays the descriptors point to stay owned by the
- * caller and must outlive the batch.
+ * non-blocking, ptycho_batch_stream); every batch call is enqueued there, so
+ * callers order their own work against it: ptycho_batch_sync, or events on
+ * that stream (the Python binding makes the batch stream wait for the
+ * caller's current stream before each call, and the caller's stream wait for
+ * the batch stream after it).  The arrays the descriptors point to stay owned
+ * by the caller and must outlive the batch.
  */
 int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t nrecon, int32_t history_rows);
 int ptycho_batch_destroy(ptycho_batch* b);
 /* Persistent workgroups of the launch for window size M (the autotuner's knob); 0 restores the default. */
 int ptycho_batch_set_grid(ptycho_batch* b, int32_t M, int32_t grid);
 int ptycho_batch_get_grid(const ptycho_batch* b, int32_t M);
-/* Gradient of every reconstruction (each grad overwritten) and its loss; losses: nullable device double[nrecon]. */
+/* Gradient of every reconstruction (each grad overwritten) and its loss; losses: nullable device double[nrecon]
+ * on the batch's device (E_ARG otherwise; nothing is enqueued then). */
 int ptycho_batch_loss_grad(ptycho_batch* b, double* losses);
 /* t <- t - alpha * grad for every reconstruction; advances the history row. */
 int ptycho_batch_update(ptycho_batch* b);

@@ -7,6 +7,7 @@ from ._binding import (  # noqa: F401
     Context,
     PtychoError,
     bin_positions,
+    gd_step_size,
     lib,
     ptycho_forward,
     ptycho_shift_probes,

@@ -47,7 +47,7 @@ EXPORTED = (
     "ptycho_batch_stream", "ptycho_box_exchange", "ptycho_set_checkpoint",
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
     "ptycho_copy_box", "ptycho_tiles_grad", "ptycho_shift_probes", "ptycho_forward_stack",
-    "ptycho_loss_grad_stack", "ptycho_loss_stack", "ptycho_tiles_grad_stack",
+    "ptycho_loss_grad_stack", "ptycho_loss_stack", "ptycho_tiles_grad_stack", "ptycho_gd_step_size",
 )
 
 
@@ -90,6 +90,8 @@ def lib() -> ctypes.CDLL:
             "ptycho_bin_positions": (ctypes.c_int, [P_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, P_i32]),
             "ptycho_validate_positions": (ctypes.c_int, [P_i32, c_i32, c_i32, c_i32, c_i32]),
             "ptycho_tile_box": (ctypes.c_int, [c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32] + [P_i32] * 8),
+            "ptycho_gd_step_size": (ctypes.c_int, [c_vp, c_i32, P_i32, c_i32, c_i32, c_i32, c_i32,
+                                                   ctypes.POINTER(c_dbl)]),
             "ptycho_check": (ctypes.c_int, [c_vp, ctypes.POINTER(c_u32)]),
             "ptycho_tile_accumulate": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i32, c_i32, c_i32, c_i32, c_vp,
                                                       c_i64, c_i32]),
@@ -166,6 +168,21 @@ def tile_box(H: int, W: int, tiles_y: int, tiles_x: int, ty: int, tx: int, halo:
     _check(lib().ptycho_tile_box(H, W, tiles_y, tiles_x, ty, tx, halo, *[ctypes.byref(x) for x in v]))
     vals = [x.value for x in v]
     return tuple(vals[:4]), tuple(vals[4:])
+
+
+def gd_step_size(probe, pos, H: int, W: int, S: int) -> float:
+    """The library's gradient-descent step length for a probe (complex64 [M, M], host or device) and
+    window corners over an H x W object with S slices (ptycho_gd_step_size)."""
+    if hasattr(probe, "detach"):
+        probe = probe.detach().cpu().numpy()
+    p = np.ascontiguousarray(np.asarray(probe), dtype=np.complex64)
+    if p.ndim != 2 or p.shape[0] != p.shape[1]:
+        raise ValueError("probe must be square [M, M]")
+    a = _pos_np(pos.detach().cpu().numpy() if hasattr(pos, "detach") else pos)
+    out = ctypes.c_double()
+    _check(lib().ptycho_gd_step_size(p.ctypes.data_as(c_vp), p.shape[0], a.ctypes.data_as(P_i32), len(a), int(H),
+                                     int(W), int(S), ctypes.byref(out)))
+    return out.value
 
 
 # ---------------------------------------------------------------------------

@@ -120,25 +120,36 @@ class Batch:
     def grid(self, M: int) -> int:
         return int(_lib().ptycho_batch_get_grid(self._h, int(M)))
 
+    def _ordered(self, call) -> None:
+        """Enqueue a batch call on the batch stream after the work already on the caller's current
+        stream (which may have written the tensors the batch reads), and make the caller's stream
+        wait for it, so that the caller sees its results in stream order."""
+        import torch
+        cur = torch.cuda.current_stream()
+        bs = torch.cuda.ExternalStream(self.stream_ptr)
+        bs.wait_stream(cur)
+        B._check(call())
+        cur.wait_stream(bs)
+
     def loss_grad(self, losses=None) -> None:
         """One batched gradient launch; losses (optional float64 [nrecon] device tensor) receives the losses."""
         if losses is not None:
             import torch
             B._need(losses, torch.float64, (len(self.recons),), "losses")
         ptr = ctypes.c_void_p(losses.data_ptr()) if losses is not None else ctypes.c_void_p(0)
-        B._check(_lib().ptycho_batch_loss_grad(self._h, ptr))
+        self._ordered(lambda: _lib().ptycho_batch_loss_grad(self._h, ptr))
 
     def update(self) -> None:
-        B._check(_lib().ptycho_batch_update(self._h))
+        self._ordered(lambda: _lib().ptycho_batch_update(self._h))
 
     def step(self) -> None:
-        B._check(_lib().ptycho_batch_step(self._h))
+        self._ordered(lambda: _lib().ptycho_batch_step(self._h))
 
     def capture(self) -> None:
         B._check(_lib().ptycho_batch_capture(self._h))
 
     def replay(self) -> None:
-        B._check(_lib().ptycho_batch_replay(self._h))
+        self._ordered(lambda: _lib().ptycho_batch_replay(self._h))
 
     def sync(self) -> None:
         B._check(_lib().ptycho_batch_sync(self._h))
@@ -151,17 +162,3 @@ class Batch:
         rows = ctypes.c_int32()
         B._check(_lib().ptycho_batch_history(self._h, out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(rows)))
         return out[: rows.value, : len(self.recons)].copy()
-
-
-def gd_step_size(probe: np.ndarray, pos: np.ndarray, H: int, W: int, S: int) -> float:
-    """alpha = 1 / (2 M^2 S max_r sum_i |P(r - r_i)|^2), the step used for every reconstruction.
-
-    The inverse of a bound on the Gauss-Newton curvature of the amplitude cost
-    over all S unit-modulus slices (S times the largest single-slice diagonal).
-    """
-    M = probe.shape[0]
-    cover = np.zeros((H, W), dtype=np.float64)
-    p2 = np.abs(np.asarray(probe)) ** 2
-    for y0, x0 in np.asarray(pos):
-        cover[y0:y0 + M, x0:x0 + M] += p2
-    return 1.0 / (2.0 * M * M * int(S) * float(cover.max()))

@@ -909,6 +909,36 @@ int ptycho_bin_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t 
   return PTYCHO_OK;
 }
 
+int ptycho_gd_step_size(const void* host_probe, int32_t M, const int32_t* host_pos, int32_t n, int32_t H,
+                        int32_t W, int32_t S, double* alpha_out) {
+  if (!host_probe || !alpha_out || n < 0 || (n > 0 && !host_pos)) return fail(PTYCHO_E_ARG, "bad arguments");
+  if (M < 1 || M > 4096 || H < 1 || W < 1 || S < 1) return fail(PTYCHO_E_ARG, "bad sizes");
+  int rc = validate_windows_host(host_pos, n, H, W, M);
+  if (rc != PTYCHO_OK) return rc;
+  // |P|^2 in double from the complex64 values, then the coverage sum_i |P(r - r_i)|^2 per pixel
+  const float* p = static_cast<const float*>(host_probe);
+  std::vector<double> p2(static_cast<size_t>(M) * M);
+  for (size_t q = 0; q < p2.size(); ++q) {
+    const double re = p[2 * q], im = p[2 * q + 1];
+    p2[q] = re * re + im * im;
+  }
+  std::vector<double> cover(static_cast<size_t>(H) * W, 0.0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t y0 = host_pos[2 * i], x0 = host_pos[2 * i + 1];
+    for (int32_t y = 0; y < M; ++y) {
+      double* row = cover.data() + static_cast<size_t>(y0 + y) * W + x0;
+      const double* src = p2.data() + static_cast<size_t>(y) * M;
+      for (int32_t x = 0; x < M; ++x) row[x] += src[x];
+    }
+  }
+  double peak = 0.0;
+  for (double c : cover) peak = c > peak ? c : peak;
+  if (!(peak > 0.0) || !std::isfinite(peak))
+    return fail(PTYCHO_E_ARG, "no pixel is covered by a non-zero probe: the step bound is infinite");
+  *alpha_out = 1.0 / (2.0 * static_cast<double>(M) * M * S * peak);
+  return PTYCHO_OK;
+}
+
 // ---------------------------------------------------------------------------
 // batched reconstructions
 // ---------------------------------------------------------------------------
@@ -916,6 +946,7 @@ int ptycho_bin_positions(const int32_t* host_pos, int32_t n, int32_t H, int32_t 
 
 struct ptycho_batch {
   int nrecon = 0;
+  int device = 0;
   hipStream_t stream = nullptr;
   int num_cu = 256;
   std::vector<ptycho_recon> host;
@@ -1066,6 +1097,7 @@ int ptycho_batch_create(ptycho_batch** out, const ptycho_recon* recons, int32_t 
     free_batch(b);
     return hip_fail(e, "batch stream");
   }
+  b->device = dev;
   // work list grouped by window size, then reconstruction, then position
   std::vector<ptycho::BatchRecon> recs(nrecon);
   std::vector<int> bounds(18, 0);
@@ -1195,6 +1227,7 @@ int ptycho_batch_get_grid(const ptycho_batch* b, int32_t M) {
 
 int ptycho_batch_loss_grad(ptycho_batch* b, double* losses) {
   if (!b) return fail(PTYCHO_E_ARG, "null batch");
+  PT_BUF(b->device, losses, static_cast<size_t>(b->nrecon) * sizeof(double), "losses");
   return batch_enqueue_loss_grad(b, losses);
 }
 

@@ -155,3 +155,37 @@ def test_binding_rejects_host_tensors_and_bad_position_shapes():
         B._need_pos(torch.zeros((3, 2), dtype=torch.int32))
     with pytest.raises(ValueError, match="CUDA tensor"):
         B._on_device(np.zeros(3), "x")
+
+
+@pytest.mark.parametrize("name,S", [("2d-256-m64", 1), ("ms8-1024-m128", 8)])
+def test_gd_step_size_matches_the_oracle(name, S):
+    """The library's step length (host helper) and the oracle's, on the same complex64 probe values."""
+    spec = ps.reduced(ps.workload(name), W=320, ny=9, nx=7, S=S)
+    probe = ps.make_probe(spec.M, spec.R, spec.C, spec.dose).astype(np.complex64)
+    pos = ps.raster_positions(spec.W, spec.M, spec.ny, spec.nx, spec.step)
+    pos[3] = (0, 0)  # a corner window as well
+    want = oracle.gd_step_size(probe.astype(np.complex128), pos, spec.W, spec.W, S)
+    got = pt.gd_step_size(probe, pos, spec.W, spec.W, S)
+    assert abs(got - want) <= 1e-12 * want
+
+
+def test_gd_step_size_errors():
+    lib = pt.lib()
+    probe = np.ones((8, 8), dtype=np.complex64)
+    pos = np.array([[0, 0], [4, 4]], dtype=np.int32)
+    out = ctypes.c_double(-1.0)
+    P = ctypes.POINTER(ctypes.c_int32)
+    assert lib.ptycho_gd_step_size(probe.ctypes.data_as(ctypes.c_void_p), 8, pos.ctypes.data_as(P), 2, 12, 12, 2,
+                                   ctypes.byref(out)) == 0
+    assert abs(out.value - 1.0 / (2 * 64 * 2 * 2.0)) <= 1e-15  # the centre pixels are covered twice
+    bad = np.array([[5, 5]], dtype=np.int32)  # leaves the 12 x 12 object
+    assert lib.ptycho_gd_step_size(probe.ctypes.data_as(ctypes.c_void_p), 8, bad.ctypes.data_as(P), 1, 12, 12, 2,
+                                   ctypes.byref(out)) == -3
+    zero = np.zeros((8, 8), dtype=np.complex64)
+    out.value = -1.0
+    assert lib.ptycho_gd_step_size(zero.ctypes.data_as(ctypes.c_void_p), 8, pos.ctypes.data_as(P), 2, 12, 12, 2,
+                                   ctypes.byref(out)) == -1
+    assert lib.ptycho_gd_step_size(probe.ctypes.data_as(ctypes.c_void_p), 8, pos.ctypes.data_as(P), 0, 12, 12, 2,
+                                   ctypes.byref(out)) == -1
+    assert out.value == -1.0  # nothing written on failure
+    assert lib.ptycho_gd_step_size(None, 8, pos.ctypes.data_as(P), 2, 12, 12, 2, ctypes.byref(out)) == -1

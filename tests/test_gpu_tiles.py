@@ -242,7 +242,6 @@ def test_direct_neighbour_add(torch_cuda, tiles):
 @pytest.mark.parametrize("batch,T", [(4, 1), (4, 3)])
 def test_alg1_walk_matches_oracle(torch_cuda, batch, T):
     import torch
-    from paper_2205_06327_amd.batch import gd_step_size
     from paper_2205_06327_amd.tilewalk import Alg1Walk, TileWalk
     spec = ps.with_overrides(ps.workload("2d-256-m64"), W=192, S=2, ny=17, nx=17, step=8, tiles=(4, 4), halo=32)
     say(f"Alg. 1 walk, 4x4 tiles of 48 px, halo 32, batch {batch}, T {T}, 2 iterations")
@@ -250,7 +249,7 @@ def test_alg1_walk_matches_oracle(torch_cuda, batch, T):
     t = to_dev(d)
     plan = TileWalk(d["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
     ctx = context(spec, spec.n)
-    alpha = 0.5 * gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
+    alpha = 0.5 * oracle.gd_step_size(d["probe"], d["pos"], spec.W, spec.W, spec.S)
     meas_sorted = t["meas"][torch.tensor(plan.order, device="cuda:0")].contiguous()
     walk = Alg1Walk(ctx, plan, t["obj"], t["probe"], meas_sorted, alpha, batch, T)
     losses = [float(walk.iteration().item()) for _ in range(2)]
