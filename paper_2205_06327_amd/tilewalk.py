@@ -196,7 +196,9 @@ class AllTilesWalk:
         return 1
 
     def device_bytes(self) -> int:
-        return sum(b.numel() * b.element_size() for b in self.bufs)
+        """Tile buffers, positions and tile indices plus the context's workspace."""
+        return sum(b.numel() * b.element_size() for b in self.bufs) + self.pos.numel() * 4 + \
+            self.tile_of_pos.numel() * 4 + self.ctx.workspace_bytes()
 
     def profile(self, enable: bool = True) -> None:
         self.ctx.profile(enable)
@@ -207,11 +209,12 @@ class AllTilesWalk:
     def check(self) -> int:
         return self.ctx.check()
 
-    def step(self, obj, probe, meas_sorted, grad):
-        """grad <- sum of the embedded tile gradients; returns the total loss (float64 [1])."""
+    def step(self, obj, probe, meas_sorted, grad, loss_per_pos=None):
+        """grad <- sum of the embedded tile gradients; returns the total loss (float64 [1]).
+        loss_per_pos: optional float64 [n] device tensor receiving f_i in tile order."""
         B.ptycho_zero_gradient(self.ctx, grad)
         B.ptycho_tiles_grad(self.ctx, obj, self.tiles, self.plan.halo, self.tile_of_pos, probe, self.pos,
-                            meas_sorted, loss=self.loss)
+                            meas_sorted, loss=self.loss, loss_per_pos=loss_per_pos)
         for k, p in enumerate(self.plan.plans):
             B.ptycho_tile_accumulate(self.ctx, self.bufs[k], p.box, grad)
         return self.loss
@@ -261,8 +264,9 @@ class StreamingTileWalk:
         self.pos_host = torch.tensor(plan.pos_sorted, dtype=torch.int32).pin_memory()
 
     def device_bytes(self) -> int:
+        """The lanes' buffers plus every lane context's workspace (the walk's whole device memory)."""
         return sum(t.numel() * t.element_size() for d in self.dev for t in d.values()) + \
-            self.loss.numel() * self.loss.element_size()
+            self.loss.numel() * self.loss.element_size() + sum(c.workspace_bytes() for c in self.ctxs)
 
     def check(self) -> int:
         st = 0
@@ -407,7 +411,8 @@ class DecomposedTileWalk:
         self.tile_loss = torch.zeros(len(plan.plans), dtype=torch.float64, device=device)
 
     def device_bytes(self) -> int:
-        return sum(b.numel() * b.element_size() for b in self.bufs)
+        """The per-tile buffers plus every lane context's workspace."""
+        return sum(b.numel() * b.element_size() for b in self.bufs) + sum(c.workspace_bytes() for c in self.ctxs)
 
     def check(self) -> int:
         st = 0

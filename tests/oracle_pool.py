@@ -119,3 +119,38 @@ class OraclePool:
 
     def __exit__(self, *exc):
         self.close()
+
+
+# ---------------------------------------------------------------------------
+# the batched workload: seeded inputs of many independent reconstructions
+# ---------------------------------------------------------------------------
+def batch_problem(spec):
+    """Seeded inputs of one reconstruction: complex64-rounded object and probe (held as complex128),
+    positions, Poisson measurements of the oracle's intensities at the truth, the oracle's step length
+    and propagator."""
+    import oracle
+    import ptycho_synth as ps
+    d = ps.build_inputs(spec)
+    H = oracle.fresnel_propagator(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
+    probe = d["probe"].astype(np.complex64).astype(np.complex128)
+    obj_true = d["obj_true"].astype(np.complex64).astype(np.complex128)
+    meas = ps.poisson_counts(oracle.forward(obj_true, probe, d["pos"], H), d["noise_seed"])
+    alpha = oracle.gd_step_size(probe, d["pos"], spec.W, spec.W, spec.S)
+    return {"obj": d["obj_eval"].astype(np.complex64).astype(np.complex128), "probe": probe, "pos": d["pos"],
+            "meas": meas, "alpha": alpha, "H": H}
+
+
+def _batch_problem_c64(spec):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(1):
+        p = batch_problem(spec)
+    return {"obj": p["obj"].astype(np.complex64), "probe": p["probe"].astype(np.complex64), "pos": p["pos"],
+            "meas": p["meas"], "alpha": p["alpha"]}
+
+
+def batch_problems(specs, workers=None, timeout: float = 600.0):
+    """batch_problem for every spec over spawned worker processes (complex64 object and probe)."""
+    n = workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(min(n, len(specs))) as pool:
+        return pool.map_async(_batch_problem_c64, list(specs), chunksize=1).get(timeout=timeout)

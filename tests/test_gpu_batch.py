@@ -36,12 +36,13 @@ def small_specs():
 
 
 def build(specs, torch):
-    from paper_2205_06327_amd.batch import Recon, gd_step_size
+    from paper_2205_06327_amd.batch import Recon
     dev = "cuda:0"
     probs, recons = [], []
     for sp in specs:
         d = problem(sp)
-        alpha = gd_step_size(d["probe"], d["pos"], sp.W, sp.W, sp.S)
+        # the step length is a caller input of both sides; the oracle computes it
+        alpha = oracle.gd_step_size(d["probe"], d["pos"], sp.W, sp.W, sp.S)
         d["alpha"] = alpha
         probs.append(d)
         recons.append(Recon(torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev),
@@ -168,3 +169,69 @@ def test_batch_one_window_size_with_an_empty_reconstruction(torch_cuda, M):
     b.update()
     b.sync()
     assert torch.equal(recons[-1].obj, empty_obj)
+
+
+def test_batch32_uneven_parity_with_autotuner_and_graph_replay(torch_cuda):
+    """The 32 uneven reconstructions of the batched workload at their own shapes (objects of 256-1024 px,
+    1-8 slices, 64- and 128-windows, Poisson doses 1e4-1e6), launch shapes chosen by the autotuner:
+    first-iteration loss (1e-5) and a gradient block on every slice (1e-4) per reconstruction, then
+    20 hipGraph-replayed gradient-descent iterations against the oracle's loss trajectory (1e-4 per
+    iteration, every reconstruction), descending monotonically.  The oracle's values are stored in
+    tests/golden/batch32_gd_trajectory.json (written by make_batch32_trajectory.py from oracle/ only)."""
+    import json
+    import os
+
+    import torch
+    from oracle_pool import batch_problems
+    from paper_2205_06327_amd.autotune import tune
+    from paper_2205_06327_amd.batch import Batch, Recon
+    with open(os.path.join(os.path.dirname(__file__), "golden", "batch32_gd_trajectory.json")) as f:
+        golden = json.load(f)
+    specs = ps.batch_specs(4)
+    assert [g["name"] for g in golden["recons"]] == [sp.name for sp in specs]
+    iters, bs = golden["iterations"], golden["block"]
+    say(f"32 uneven reconstructions: inputs and oracle measurements ({sum(sp.n for sp in specs)} positions)")
+    probs = batch_problems(specs)
+    dev = "cuda:0"
+    recons = []
+    for sp, p, g in zip(specs, probs, golden["recons"]):
+        assert (sp.M, sp.S, sp.W, sp.n) == (g["M"], g["S"], g["W"], g["n"])
+        assert abs(p["alpha"] - g["alpha"]) <= 1e-12 * g["alpha"], sp.name  # the same inputs as the golden run
+        recons.append(Recon(torch.tensor(p["obj"], device=dev), torch.tensor(p["probe"], device=dev),
+                            torch.tensor(p["pos"], dtype=torch.int32, device=dev),
+                            torch.tensor(p["meas"], dtype=torch.float32, device=dev),
+                            sp.wavelength_A, sp.dz_A, sp.pixel_A, p["alpha"]))
+    del probs
+    b = Batch(recons, history_rows=iters)
+    tuned = tune(b, reps=2, rounds=1, cache_path=None)
+    say(f"  autotuner: 64-windows {tuned[64]} workgroups, 128-windows {tuned[128]}")
+    losses = torch.zeros(len(recons), dtype=torch.float64, device=dev)
+    b.loss_grad(losses)
+    b.sync()
+    L = losses.cpu().numpy()
+    worst_l, worst_g = 0.0, 0.0
+    for k, (sp, r, g) in enumerate(zip(specs, recons, golden["recons"])):
+        el = abs(L[k] - g["loss"][0]) / g["loss"][0]
+        by, bx = g["block_origin"]
+        ref = np.array(g["grad_block_re"]) + 1j * np.array(g["grad_block_im"])
+        eg = rel_l2(r.grad[:, by:by + bs, bx:bx + bs].cpu().numpy(), ref)
+        worst_l, worst_g = max(worst_l, el), max(worst_g, eg)
+        assert el <= 1e-5, (sp.name, el)
+        assert eg <= 1e-4, (sp.name, eg)
+    say(f"  first iteration: worst loss rel err {worst_l:.2e}, worst gradient block rel L2 {worst_g:.2e}")
+    b.reset_history()
+    b.capture()
+    for _ in range(iters):
+        b.replay()
+    b.sync()
+    hist = b.history()
+    assert hist.shape == (iters, len(specs))
+    worst = 0.0
+    for k, (sp, g) in enumerate(zip(specs, golden["recons"])):
+        ref = np.array(g["loss"])
+        assert np.all(np.diff(ref) < 0), sp.name
+        assert np.all(np.diff(hist[:, k]) < 0), sp.name
+        e = float(np.max(np.abs(hist[:, k] - ref) / ref))
+        worst = max(worst, e)
+        assert e <= 1e-4, (sp.name, e)
+    say(f"  {iters} replayed iterations: worst per-iteration loss rel err {worst:.2e}")

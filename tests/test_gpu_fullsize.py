@@ -3,10 +3,14 @@
 * 8 slices of 1024^2, 4096 positions: the autograd.Function gradient (fused
   adjoint kernel) against central finite differences (h = 1e-3) of the FP64
   oracle loss on 64 random voxels, and against the oracle gradient there.
-* 16 slices of 2048^2, 16632 positions, 4x4 tiles with a 64 px halo, run in
-  the launch configuration the benchmark times (resident tile walk): Parseval
-  for every pattern, sampled patterns and per-position losses, a gradient
-  block across the corner of four tiles, and decomposed vs undecomposed.
+* 16 slices of 2048^2, 16632 positions, 4x4 tiles with a 64 px halo.  The
+  launch configuration the benchmark times -- every tile's gradient in one
+  persistent launch (AllTilesWalk, ptycho_tiles_grad), then the stitch -- and,
+  as a second case, the resident walk with one launch per tile on two lanes
+  (ResidentTileWalk, ptycho_tile_grad).  Each is checked against the oracle on
+  sampled per-position losses and on a gradient block across the corner of
+  four tiles, and against the undecomposed GPU gradient; Parseval holds for
+  every pattern and sampled patterns match the oracle.
 """
 import numpy as np
 import pytest
@@ -92,12 +96,13 @@ def test_autograd_gradient_vs_finite_differences_8_slices(torch_cuda):
         assert abs(float(L.item()) - L_ref) <= 1e-5 * L_ref
 
 
-def test_tiled_16_slices_2048_sampled_parity(torch_cuda):
+@pytest.fixture(scope="module")
+def fullsize(torch_cuda):
+    """Inputs of the 16 x 2048^2 workload, oracle values on a sample, and the undecomposed GPU gradient."""
     import torch
     import paper_2205_06327_amd as pt
-    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, TileWalk
     spec = ps.workload("ms16-2048-m128-tiles4x4")
-    say("16 x 2048^2, 16632 positions, 4x4 tiles: sampled parity in the benchmark's launch configuration")
+    say("16 x 2048^2, 16632 positions, 4x4 tiles: inputs, oracle sample, undecomposed gradient")
     d = ps.build_inputs(spec, workers=8)
     H = oracle.fresnel_propagator(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
     pos = d["pos"]
@@ -134,26 +139,7 @@ def test_tiled_16_slices_2048_sampled_parity(torch_cuda):
         I_ref = pool.intensities(pos[sample])
         res = pool.loss_grad(exact, pos)
     assert rel_l2(I.cpu().numpy(), I_ref) <= 1e-5
-    # tile walk exactly as benchmarked
-    plan = TileWalk(pos, W, W, M, spec.tiles, spec.halo)
-    walk = ResidentTileWalk(ctx, plan)
-    order = torch.tensor(plan.order, device=dev)
-    meas_sorted = meas_d[order].contiguous()
-    grad = torch.empty_like(obj)
-    tl = walk.step(obj, probe, meas_sorted, grad)
-    walk.check()
-    lpp = torch.zeros(len(pos), dtype=torch.float64, device=dev)
-    gfull = torch.empty_like(obj)
-    lfull, _ = pt.ptycho_loss_grad(ctx, obj, probe, pos_d, meas_d, grad=gfull, loss_per_pos=lpp)
-    ctx.check()
-    dec = float(torch.linalg.vector_norm(grad - gfull) / torch.linalg.vector_norm(gfull))
-    say(f"  decomposed vs undecomposed {dec:.2e}")
-    assert dec <= 1e-6
-    assert abs(float(tl.sum()) - float(lfull.item())) <= 1e-9 * float(lfull.item())
     lookup = {int(i): r for i, r in zip(exact, res)}
-    lpp_h = lpp.cpu().numpy()
-    ref_l = np.array([lookup[int(i)][0] for i in sample])
-    np.testing.assert_allclose(lpp_h[sample], ref_l, rtol=1e-5)
     blk = np.zeros((S, bs, bs), dtype=np.complex128)
     for i in cov_blk:
         y0, x0 = pos[i]
@@ -161,7 +147,96 @@ def test_tiled_16_slices_2048_sampled_parity(torch_cuda):
         ys, xs = max(by, y0), max(bx, x0)
         ye, xe = min(by + bs, y0 + M), min(bx + bs, x0 + M)
         blk[:, ys - by:ye - by, xs - bx:xe - bx] += patch[:, ys - y0:ye - y0, xs - x0:xe - x0]
+    gfull = torch.empty_like(obj)
+    lfull, _ = pt.ptycho_loss_grad(ctx, obj, probe, pos_d, meas_d, grad=gfull)
+    ctx.check()
+    return {"spec": spec, "pos": pos, "ctx": ctx, "obj": obj, "probe": probe, "meas": meas_d, "gfull": gfull,
+            "lfull": float(lfull.item()), "sample": sample, "ref_loss": np.array([lookup[int(i)][0] for i in sample]),
+            "blk": blk, "block": (by, bx, bs), "cov_blk": cov_blk, "lookup": lookup}
+
+
+def _check_decomposed(fs, grad, loss_total, lpp_sorted, order, what):
+    import torch
+    by, bx, bs = fs["block"]
+    dec = float(torch.linalg.vector_norm(grad - fs["gfull"]) / torch.linalg.vector_norm(fs["gfull"]))
+    say(f"  {what}: decomposed vs undecomposed {dec:.2e}")
+    assert dec <= 1e-6
+    assert abs(loss_total - fs["lfull"]) <= 1e-9 * fs["lfull"]
+    # per-position losses (tile order -> scan order) against the oracle on the sample
+    lpp = np.empty(len(order))
+    lpp[order] = lpp_sorted.cpu().numpy()
+    np.testing.assert_allclose(lpp[fs["sample"]], fs["ref_loss"], rtol=1e-5)
     got = grad[:, by:by + bs, bx:bx + bs].cpu().numpy()
-    e = rel_l2(got, blk)
-    say(f"  gradient block rel L2 {e:.2e} over {len(cov_blk)} positions")
+    e = rel_l2(got, fs["blk"])
+    say(f"  {what}: gradient block rel L2 {e:.2e} over {len(fs['cov_blk'])} positions")
     assert e <= 1e-4
+
+
+def test_tiled_16_slices_2048_all_tiles_launch(fullsize):
+    """The benchmark's launch configuration: every tile's gradient in one persistent launch
+    (ptycho_tiles_grad into per-tile buffers on the extended boxes), then the 16 stitches."""
+    import torch
+    from paper_2205_06327_amd.tilewalk import AllTilesWalk, TileWalk
+    fs = fullsize
+    spec, ctx = fs["spec"], fs["ctx"]
+    plan = TileWalk(fs["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    walk = AllTilesWalk(ctx, plan)
+    order = torch.tensor(plan.order, device="cuda:0")
+    meas_sorted = fs["meas"][order].contiguous()
+    grad = torch.empty_like(fs["obj"])
+    lpp = torch.zeros(plan.n, dtype=torch.float64, device="cuda:0")
+    loss = walk.step(fs["obj"], fs["probe"], meas_sorted, grad, loss_per_pos=lpp)
+    assert walk.check() == 0
+    _check_decomposed(fs, grad, float(loss.item()), lpp, plan.order, "all tiles in one launch")
+    # each of the four tiles around the corner holds its own positions' gradient on the block
+    by, bx, bs = fs["block"]
+    M, S, pos = spec.M, spec.S, fs["pos"]
+    owner = oracle.bin_positions(pos, spec.W, spec.W, M, *spec.tiles)
+    seen = 0
+    for k in sorted({int(owner[i]) for i in fs["cov_blk"]}):
+        ref = np.zeros((S, bs, bs), dtype=np.complex128)
+        for i in fs["cov_blk"]:
+            if owner[i] != k:
+                continue
+            y0, x0 = pos[i]
+            patch = fs["lookup"][int(i)][1]
+            ys, xs = max(by, y0), max(bx, x0)
+            ye, xe = min(by + bs, y0 + M), min(bx + bs, x0 + M)
+            ref[:, ys - by:ye - by, xs - bx:xe - bx] += patch[:, ys - y0:ye - y0, xs - x0:xe - x0]
+        ey0, ex0, _, _ = plan.plans[k].box
+        got = walk.bufs[k][:, by - ey0:by - ey0 + bs, bx - ex0:bx - ex0 + bs].cpu().numpy()
+        e = rel_l2(got, ref)
+        say(f"  tile {k} buffer on the corner block: rel L2 {e:.2e}")
+        assert e <= 1e-4
+        seen += 1
+    assert seen == 4
+
+
+def test_tiled_16_slices_2048_resident_walk(fullsize):
+    """The resident walk: one launch per tile (ptycho_tile_grad) on two alternating lanes, each tile's
+    gradient stitched into the global gradient in tile order."""
+    import torch
+    import paper_2205_06327_amd as pt
+    from paper_2205_06327_amd.tilewalk import ResidentTileWalk, TileWalk
+    fs = fullsize
+    spec, ctx = fs["spec"], fs["ctx"]
+    plan = TileWalk(fs["pos"], spec.W, spec.W, spec.M, spec.tiles, spec.halo)
+    walk = ResidentTileWalk(ctx, plan)
+    order = torch.tensor(plan.order, device="cuda:0")
+    meas_sorted = fs["meas"][order].contiguous()
+    grad = torch.empty_like(fs["obj"])
+    tl = walk.step(fs["obj"], fs["probe"], meas_sorted, grad)
+    assert walk.check() == 0
+    # per-position losses of this walk's kernels: one tile call per tile with loss_per_pos
+    lpp = torch.zeros(plan.n, dtype=torch.float64, device="cuda:0")
+    scratch = torch.empty((spec.S, *plan.max_box), dtype=torch.complex64, device="cuda:0")
+    for p in plan.plans:
+        if p.hi == p.lo:
+            continue
+        ey0, ex0, eh, ew = p.box
+        tg = scratch.view(-1)[: spec.S * eh * ew].view(spec.S, eh, ew)
+        pt.ptycho_tile_grad(ctx, fs["obj"][:, ey0:ey0 + eh, ex0:ex0 + ew], p.box, p.tile, plan.halo, plan.H, plan.W,
+                            fs["probe"], walk.pos[p.lo:p.hi], meas_sorted[p.lo:p.hi], tile_grad=tg,
+                            loss_per_pos=lpp[p.lo:p.hi])
+    ctx.check()
+    _check_decomposed(fs, grad, float(tl.sum().item()), lpp, plan.order, "resident walk, two lanes")
