@@ -26,10 +26,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "probe-positions/s, forward+adjoint gradient, fused vs plain; % of HBM roofline"
-HBM_PEAK_GBS = 8000.0
-# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz; the kernels are compiled without packed FP32 instructions.
-FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-FP32_PACKED_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+FP32_PEAK_TFLOPS = 157.3          # MI355X FP32 vector, published (packed FMA)
+# 256 CUs x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz: the FP32 rate without packed instructions, which the
+# kernels are compiled without
+FP32_NONPACKED_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+HBM_TARGET_FRAC = 0.5             # planning target of the 16-slice workload
 
 
 def kernel_source_sha256() -> str:
@@ -158,10 +160,21 @@ def cpu_baseline(spec, inputs, sample_count, cores):
             t0 = time.perf_counter()
             pool.map(_cpu_job, range(len(idx)), chunksize=chunk)
             dt = time.perf_counter() - t0
+        # one core: the same oracle in this process, single-threaded, on the first positions of the sample
+        n1 = min(len(idx), 48)
+        _cpu_job(0)
+        t1 = time.perf_counter()
+        for i in range(n1):
+            _cpu_job(i)
+        dt1 = time.perf_counter() - t1
     return {"value": len(idx) / dt, "unit": "positions/s", "cores": cores, "kind": "oracle",
             "sample": f"{len(idx)} positions spread evenly over the {len(pos)}-position scan, FP64 numpy oracle "
                       f"(forward + loss + adjoint per position), one single-threaded process per core, "
-                      f"{dt:.2f} s wall, {dt * cores:.0f} core-seconds"}
+                      f"{dt:.2f} s wall, {dt * cores:.0f} core-seconds",
+            "per_core_value": round(n1 / dt1, 2),
+            "per_core_sample": f"{n1} positions in one single-threaded process, {dt1:.2f} s",
+            "host_cpu_count": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
 
 
 def run_batch(args, cores):
@@ -172,7 +185,7 @@ def run_batch(args, cores):
     import ptycho_synth as ps
     import paper_2205_06327_amd as pt
     from paper_2205_06327_amd.autotune import tune
-    from paper_2205_06327_amd.batch import Batch, Recon, gd_step_size
+    from paper_2205_06327_amd.batch import Batch, Recon
 
     dev = torch.device("cuda:0")
     specs = ps.batch_specs(4)
@@ -188,7 +201,7 @@ def run_batch(args, cores):
         g = torch.Generator(device=dev)
         g.manual_seed(sp.seed)
         meas = torch.poisson(I, generator=g)
-        alpha = gd_step_size(d["probe"], d["pos"], sp.W, sp.W, sp.S)
+        alpha = pt.gd_step_size(d["probe"], d["pos"], sp.W, sp.W, sp.S)
         recons.append(Recon(torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev), probe, pos, meas,
                             sp.wavelength_A, sp.dz_A, sp.pixel_A, alpha))
         total_pos += sp.n
@@ -246,7 +259,6 @@ def run_alg1(args, cores):
 
     import ptycho_synth as ps
     import paper_2205_06327_amd as pt
-    from paper_2205_06327_amd.batch import gd_step_size
     from paper_2205_06327_amd.tilewalk import Alg1Walk, TileWalk
 
     dev = torch.device("cuda:0")
@@ -264,7 +276,7 @@ def run_alg1(args, cores):
     meas = torch.poisson(I, generator=gen)
     del I
     obj0 = torch.tensor(inputs["obj_eval"], dtype=torch.complex64, device=dev)
-    alpha = 0.5 * gd_step_size(inputs["probe"], inputs["pos"], W, W, S)
+    alpha = 0.5 * pt.gd_step_size(inputs["probe"], inputs["pos"], W, W, S)
     batch = 64  # positions per tile per update: 16 updates per tile per iteration
     iters = max(args.steps, 1)
     counts = [p.hi - p.lo for p in plan.plans]
@@ -317,6 +329,7 @@ def main():
                     help="all: every tile's gradient in one launch; lanes: one launch per tile on alternating streams")
     ap.add_argument("--checkpoint", type=int, default=1,
                     help="keep every k-th incident wave, recompute the others in the adjoint sweep")
+    ap.add_argument("--no-walk-tune", action="store_true", help="skip the walk-shape autotuner report")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy three times (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -412,36 +425,42 @@ def main():
     Bpos = algorithmic_bytes(M, S)
     Fpos = algorithmic_flops(M, S)
     k_s = k_ms / 1e3
+    per_launch = k_pos / max(k_launches, 1)
     gbs = k_pos * Bpos / k_s / 1e9
     tflops = k_pos * Fpos / k_s / 1e12
     roofline = {
-        "bound": "alu",
-        "achieved": round(tflops, 3),
-        "peak": round(FP32_PEAK_TFLOPS, 2),
-        "unit": "TFLOP/s",
-        "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+        "bound": "hbm",
+        "achieved": round(gbs, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gbs / HBM_PEAK_GBS, 4),
         "traffic": None,
         "kernel": f"fused_kernel<{M}, 2> (loss + gradient)",
         "avg_launch_ms": round(k_ms / max(k_launches, 1), 4),
         "launches": k_launches,
-        "positions_per_launch": round(k_pos / max(k_launches, 1), 1),
+        "positions_per_launch": round(per_launch, 1),
         "algorithmic_bytes_per_position": Bpos,
         "algorithmic_flops_per_position": Fpos,
-        "hbm_achieved_GBs": round(gbs, 1),
-        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
-        "frac_vs_packed_fp32_peak": round(tflops / FP32_PACKED_PEAK_TFLOPS, 4),
+        "hbm_target_frac": HBM_TARGET_FRAC,
+        "hbm_target_met": bool(gbs / HBM_PEAK_GBS >= HBM_TARGET_FRAC),
+        # the same launches against the FP32 vector peaks: the published (packed FMA) one and the rate
+        # without packed instructions
+        "fp32_tflops": round(tflops, 3),
+        "frac_vs_fp32_peak": round(tflops / FP32_PEAK_TFLOPS, 4),
+        "frac_vs_fp32_nonpacked_peak": round(tflops / FP32_NONPACKED_PEAK_TFLOPS, 4),
+        # hardware float atomics of the gradient scatter (2 S M^2 per position)
+        "gradient_atomics_per_s": round(k_pos * 2 * S * M * M / k_s, 1),
     }
-    # the walk's launches overlap (two lanes), so the per-launch rate above is the conservative one;
-    # this is the same algorithmic work over the wall time of the whole step
-    roofline["step_tflops"] = round(spec.n * Fpos / (ms_per_step / 1e3) / 1e12, 3)
-    roofline["step_frac"] = round(roofline["step_tflops"] / FP32_PEAK_TFLOPS, 4)
+    # the same algorithmic work over the wall time of the whole step (zeroing and stitches included)
+    roofline["step_GBs"] = round(spec.n * Bpos / (ms_per_step / 1e3) / 1e9, 1)
+    roofline["step_frac"] = round(roofline["step_GBs"] / HBM_PEAK_GBS, 4)
     hbm_roofline_pos = HBM_PEAK_GBS * 1e9 / Bpos
     tr = measured_traffic(spec.name)
     if tr is not None:
-        per_launch = tr["traffic_bytes_per_dispatch"]
-        roofline["traffic"] = round(per_launch)
-        roofline["traffic_bytes_per_position"] = round(per_launch / (k_pos / max(k_launches, 1)))
-        roofline["traffic_over_algorithmic"] = round(per_launch / ((k_pos / max(k_launches, 1)) * Bpos), 3)
+        traffic = tr["traffic_bytes_per_dispatch"]
+        roofline["traffic"] = round(traffic)
+        roofline["traffic_bytes_per_position"] = round(traffic / per_launch)
+        roofline["traffic_over_algorithmic"] = round(traffic / (per_launch * Bpos), 3)
 
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "positions/s", "n_gpus": 1, "steps": args.steps,
@@ -533,34 +552,72 @@ def main():
             "max_rel_l2_vs_undecomposed": worst_n,
         }
         del dwalk, acc, gfull
-        # streaming walk: object, measurements and gradient in pinned host memory
-        log("streaming tile walk (host-resident inputs)")
+        # Peak device footprint, the library's workspaces included: the undecomposed gradient (every input
+        # resident, one context) against the streaming tile walk (inputs and the global gradient in pinned
+        # host memory, the device holding per lane one tile's boxes, patterns and a context).  Each walk is
+        # measured as the drop of free device memory (hipMemGetInfo) from before its contexts and buffers
+        # exist to after a step.
+        log("streaming tile walk (host-resident inputs) and device footprints")
         obj_h = obj.cpu().pin_memory()
         meas_h = meas.cpu().pin_memory()
         grad_h = torch.empty((S, W, W), dtype=torch.complex64).pin_memory()
         del walk
-        torch.cuda.synchronize()
+        undec = {"object": obj.numel() * 8, "patterns": meas.numel() * 4, "gradient": grad.numel() * 8,
+                 "positions": spec.n * 8, "context_workspace": int(ctx.workspace_bytes())}
+        undec["total"] = sum(undec.values())
+        footprint = {"undecomposed_resident": undec, "streaming": []}
+        for lanes, ck in ((2, 1), (1, 4)):
+            # torch's tensors: the peak of torch's allocations over the walk; the library's own device
+            # memory (contexts: tables, wave store, partial sums): the drop of free device memory that
+            # torch's reserved memory does not account for
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            alloc0, reserved0 = torch.cuda.memory_allocated(), torch.cuda.memory_reserved()
+            torch.cuda.reset_peak_memory_stats()
+            free0 = torch.cuda.mem_get_info()[0]
+            c0 = pt.Context(M, S, spec.wavelength_A, spec.dz_A, spec.pixel_A, max_positions=plan.max_count)
+            c0.set_checkpoint(ck)
+            sw = StreamingTileWalk(plan, c0, device=dev, lanes=lanes)
+            sw.step(obj_h, probe, meas_h, grad_h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sw.step(obj_h, probe, meas_h, grad_h)
+            torch.cuda.synchronize()
+            st_ms = (time.perf_counter() - t0) * 1e3
+            torch_peak = torch.cuda.max_memory_allocated() - alloc0
+            lib_bytes = (free0 - torch.cuda.mem_get_info()[0]) - (torch.cuda.memory_reserved() - reserved0)
+            peak = torch_peak + lib_bytes
+            sw.check()
+            sdiff = float(torch.linalg.vector_norm(grad_h.to(dev) - grad) / torch.linalg.vector_norm(grad))
+            footprint["streaming"].append({
+                "lanes": lanes, "wave_checkpoint_interval": ck,
+                "ms_per_step_including_pcie": round(st_ms, 2),
+                "positions_per_s_including_pcie": round(spec.n / (st_ms / 1e3), 1),
+                "device_bytes_accounted": int(sw.device_bytes()),
+                "context_workspaces_bytes": int(sum(c.workspace_bytes() for c in sw.ctxs)),
+                "device_peak_bytes_measured": int(peak),
+                "measured_torch_peak_bytes": int(torch_peak),
+                "measured_library_bytes": int(lib_bytes),
+                "peak_vs_undecomposed": round(peak / undec["total"], 4),
+                "rel_l2_vs_resident": sdiff,
+            })
+            log(f"streaming, {lanes} lane(s), k = {ck}: {st_ms:.1f} ms, device peak {peak / 1e6:.0f} MB "
+                f"(undecomposed {undec['total'] / 1e6:.0f} MB)")
+            del sw, c0
+        out["footprint"] = footprint
+        del obj_h, meas_h, grad_h
         torch.cuda.empty_cache()
-        base_alloc = torch.cuda.memory_allocated()
-        torch.cuda.reset_peak_memory_stats()
-        sw = StreamingTileWalk(plan, ctx, device=dev)
-        sw.step(obj_h, probe, meas_h, grad_h)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sw.step(obj_h, probe, meas_h, grad_h)
-        torch.cuda.synchronize()
-        st_ms = (time.perf_counter() - t0) * 1e3
-        peak = torch.cuda.max_memory_allocated() - base_alloc
-        sdiff = float(torch.linalg.vector_norm(grad_h.to(dev) - grad) / torch.linalg.vector_norm(grad))
-        out["streaming"] = {
-            "ms_per_step_including_pcie": round(st_ms, 2),
-            "positions_per_s_including_pcie": round(spec.n / (st_ms / 1e3), 1),
-            "device_bytes_per_tile_walk": sw.device_bytes(),
-            "device_peak_bytes_measured": int(peak),
-            "resident_inputs_bytes": int(obj.numel() * 8 + meas.numel() * 4 + grad.numel() * 8),
-            "rel_l2_vs_resident": sdiff,
-        }
-        del sw, obj_h, meas_h, grad_h
+
+    if not args.no_walk_tune:
+        # the walk-shape autotuner on this workload (its own context; the timed run above used the defaults)
+        from paper_2205_06327_amd.autotune import tune_walk
+        log("walk-shape autotuner")
+        ctx_t = pt.Context(M, S, spec.wavelength_A, spec.dz_A, spec.pixel_A, max_positions=spec.n)
+        out["walk_autotuner"] = tune_walk(ctx_t, plan, obj, probe, meas, grad, reps=3, rounds=2, cache_path=None)
+        log(f"walk autotuner: {out['walk_autotuner']['walk']} / {out['walk_autotuner']['lanes']} lane(s) / "
+            f"k = {out['walk_autotuner']['checkpoint']}, {out['walk_autotuner']['ms']:.2f} ms per step")
+        del ctx_t
+        torch.cuda.empty_cache()
 
     if not args.no_plain:
         npl = min(args.plain_positions, spec.n)

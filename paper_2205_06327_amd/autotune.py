@@ -1,4 +1,4 @@
-"""Launch-shape autotuner for batched reconstructions.
+"""Launch-shape autotuners: batched reconstructions and the tile walk of one reconstruction.
 
 For every window-size class of a batch the persistent launch can use a
 different number of workgroups (the register and LDS budget allows one
@@ -92,3 +92,74 @@ def tune(batch: Batch, reps: int = 3, cache_path: Optional[str] = DEFAULT_CACHE,
             json.dump(cache, f, indent=1)
         os.replace(tmp, cache_path)
     return {64: best[64], 128: best[128], "ms": t_best, "cached": False}
+
+
+# ---------------------------------------------------------------------------
+# tile walk of one large reconstruction: walk shape and wave checkpoint interval
+# ---------------------------------------------------------------------------
+def walk_signature(ctx, plan, device_name: str) -> str:
+    """Device + window size, slices, object, tile grid, halo and the per-tile position counts, hashed."""
+    shape = [ctx.M, ctx.S, plan.H, plan.W, list(plan.tiles), plan.halo, [p.hi - p.lo for p in plan.plans]]
+    h = hashlib.sha1(json.dumps([device_name, shape]).encode()).hexdigest()[:16]
+    return f"{device_name}:walk:{h}"
+
+
+def _make_walk(ctx, plan, kind: str, lanes: int):
+    from .tilewalk import AllTilesWalk, ResidentTileWalk
+    if kind == "all":
+        return AllTilesWalk(ctx, plan)
+    return ResidentTileWalk(ctx, plan, lanes=lanes)
+
+
+def tune_walk(ctx, plan, obj, probe, meas_sorted, grad, reps: int = 3, rounds: int = 2,
+              checkpoints=(1, 2, 4), lanes=(1, 2, 3), cache_path: Optional[str] = DEFAULT_CACHE,
+              use_cache: bool = True) -> Dict:
+    """Pick the tile walk of a decomposed gradient step: every tile in one launch ("all") or one launch
+    per tile on 1-3 alternating lanes ("lanes"), and the interval k at which the fused kernel keeps
+    incident waves (the others are recomputed in the adjoint sweep).  Each candidate's step is timed
+    with HIP events over `reps` steps, once per round (rounds interleave the candidates); the lowest
+    median wins and is applied to ctx (ptycho_set_checkpoint).  Returns {"walk", "lanes",
+    "checkpoint", "ms", "timings", "cached"}; the choice is cached per device and shape."""
+    import torch
+    dev = torch.cuda.get_device_properties(0)
+    key = walk_signature(ctx, plan, dev.name)
+    cache = {}
+    if cache_path and use_cache and os.path.exists(cache_path):
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        c = cache[key]
+        ctx.set_checkpoint(int(c["checkpoint"]))
+        return {**c, "cached": True}
+    cands = [("all", 1, k) for k in checkpoints] + [("lanes", n, k) for n in lanes for k in checkpoints]
+    times = {c: [] for c in cands}
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(max(1, int(rounds))):
+        for kind, n, k in cands:
+            ctx.set_checkpoint(k)
+            walk = _make_walk(ctx, plan, kind, n)
+            walk.step(obj, probe, meas_sorted, grad)  # warm (and the lanes' contexts take k)
+            torch.cuda.synchronize()
+            start.record()
+            for _ in range(reps):
+                walk.step(obj, probe, meas_sorted, grad)
+            stop.record()
+            stop.synchronize()
+            times[(kind, n, k)].append(start.elapsed_time(stop) / reps)
+            del walk
+    best = min(cands, key=lambda c: (sorted(times[c])[len(times[c]) // 2], c))
+    kind, n, k = best
+    ctx.set_checkpoint(k)
+    result = {"walk": kind, "lanes": n, "checkpoint": k, "ms": sorted(times[best])[len(times[best]) // 2],
+              "timings": {f"{c[0]}/{c[1]}/k{c[2]}": round(sorted(v)[len(v) // 2], 3) for c, v in times.items()}}
+    if cache_path:
+        cache[key] = result
+        os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+        tmp = cache_path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1)
+        os.replace(tmp, cache_path)
+    return {**result, "cached": False}
