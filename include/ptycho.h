@@ -201,6 +201,37 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
                      int32_t grad_ld, uint32_t flags, const double* grad_scale);
 
 /*
+ * ptycho_loss_grad_static: ptycho_loss_grad without a context and without any
+ * device allocation, for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops, harnesses that forbid hipMalloc).
+ * The arguments mean what they mean for ptycho_create (M, S, wavelength_A,
+ * dz_A, pixel_A, stream) and ptycho_loss_grad (the rest, one probe for all
+ * positions); results equal ptycho_loss_grad's up to the order of the
+ * gradient atomics (and the last bit of the FP32 tables, which are built in
+ * FP64 on the device here).
+ *
+ * Workspace: one device array of 256 MiB per GPU, built into the library and
+ * held from the first call on that GPU until the process ends (the first call
+ * on a device resolves its address; make it outside graph capture).  It holds
+ * the tables, the status word, the per-position losses (hence at most 2^20
+ * positions per call: PTYCHO_E_CAPACITY beyond) and the incident-wave store;
+ * the checkpoint interval (see ptycho_set_checkpoint) and the number of
+ * workgroups are chosen so that the store fits (M = 128, S = 16: interval 4).
+ * Every call on a GPU uses the same array: calls that overlap on one GPU (two
+ * streams, two host threads) race and must be serialised by the caller.
+ * Windows outside the object are skipped (loss 0) but cannot be reported
+ * here: validate positions first (ptycho_validate_positions).
+ * Errors as for ptycho_create / ptycho_loss_grad (the caller's buffers are
+ * checked the same way); a call rejected by its size, shape, flag or pointer
+ * checks makes no HIP call at all.
+ */
+int ptycho_loss_grad_static(int32_t M, int32_t S, double wavelength_A, double dz_A, double pixel_A,
+                            void* stream, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
+                            int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
+                            double* loss, double* loss_per_pos, void* grad, int64_t grad_slice_stride,
+                            int32_t grad_ld, uint32_t flags, const double* grad_scale);
+
+/*
  * ptycho_loss_grad_probe: ptycho_loss_grad plus the gradient with respect to
  * the probe, probe_grad = dF/dRe P + i dF/dIm P = sum_i chi_{0,i} conj(t_0[window_i])
  * (chi_0 the adjoint wave at the first slice, Eq. 2 applied to psi_0 = P),

@@ -14,6 +14,7 @@ from ._binding import (  # noqa: F401
     split_positions,
     ptycho_loss,
     ptycho_loss_grad,
+    ptycho_loss_grad_static,
     ptycho_tile_accumulate,
     ptycho_tile_grad,
     ptycho_tiles_grad,

@@ -48,6 +48,7 @@ EXPORTED = (
     "ptycho_box_axpy", "ptycho_potential_transmission", "ptycho_potential_gradient", "ptycho_loss_grad_probe",
     "ptycho_copy_box", "ptycho_tiles_grad", "ptycho_shift_probes", "ptycho_forward_stack",
     "ptycho_loss_grad_stack", "ptycho_loss_stack", "ptycho_tiles_grad_stack", "ptycho_gd_step_size",
+    "ptycho_loss_grad_static",
 )
 
 
@@ -78,6 +79,9 @@ def lib() -> ctypes.CDLL:
             "ptycho_reserve": (ctypes.c_int, [c_vp, c_i32]),
             "ptycho_workspace_bytes": (c_i64, [c_vp]),
             "ptycho_forward": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp]),
+            "ptycho_loss_grad_static": (ctypes.c_int, [c_i32, c_i32, c_dbl, c_dbl, c_dbl, c_vp, c_vp, c_i32, c_i32,
+                                                         c_i64, c_i32, c_vp, c_vp, c_i32, c_vp, c_vp, c_vp, c_vp,
+                                                         c_i64, c_i32, c_u32, c_vp]),
             "ptycho_loss_grad": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32, c_vp,
                                                 c_vp, c_vp, c_vp, c_i64, c_i32, c_u32, c_vp]),
             "ptycho_loss_grad_probe": (ctypes.c_int, [c_vp, c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_i32,
@@ -413,6 +417,39 @@ def ptycho_loss_grad(ctx: Context, obj, probe, pos, meas, grad=None, loss=None, 
                                             c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()), c_vp(loss.data_ptr()),
                                             lpp, c_vp(grad.data_ptr()), grad.stride(0), grad.stride(1),
                                             c_vp(probe_grad.data_ptr()), flags, gs))
+    return loss, grad
+
+
+def ptycho_loss_grad_static(M: int, wavelength_A: float, dz_A: float, pixel_A: float, obj, probe, pos, meas,
+                            grad=None, loss=None, loss_per_pos=None, accumulate: bool = False, grad_scale=None):
+    """ptycho_loss_grad without a context (ptycho_loss_grad_static): the library's own static device
+    workspace instead of a context's allocations; on torch's current stream.  S comes from obj."""
+    torch = _torch()
+    S, H, W, ss, ld = _obj_geometry(obj)
+    n = _need_pos(pos)
+    _need(probe, torch.complex64, (M, M), "probe")
+    _need(meas, torch.float32, (n, M, M), "meas")
+    if grad is None:
+        grad = torch.empty((S, H, W), dtype=torch.complex64, device=obj.device)
+    if grad.dtype != torch.complex64 or grad.dim() != 3 or tuple(grad.shape) != (S, H, W) or grad.stride(2) != 1:
+        raise ValueError("grad must be complex64 [S, H, W] with unit stride along W")
+    if loss is None:
+        loss = torch.zeros(1, dtype=torch.float64, device=obj.device)
+    _need(loss, torch.float64, (1,), "loss")
+    lpp = c_vp(0)
+    if loss_per_pos is not None:
+        _need(loss_per_pos, torch.float64, (n,), "loss_per_pos")
+        lpp = c_vp(loss_per_pos.data_ptr())
+    gs = c_vp(0)
+    if grad_scale is not None:
+        _need(grad_scale, torch.float64, (1,), "grad_scale")
+        gs = c_vp(grad_scale.data_ptr())
+    flags = PTYCHO_ACCUMULATE if accumulate else 0
+    _check(lib().ptycho_loss_grad_static(int(M), S, float(wavelength_A), float(dz_A), float(pixel_A),
+                                         c_vp(_stream_ptr()), c_vp(obj.data_ptr()), H, W, ss, ld,
+                                         c_vp(probe.data_ptr()), c_vp(pos.data_ptr()), n, c_vp(meas.data_ptr()),
+                                         c_vp(loss.data_ptr()), lpp, c_vp(grad.data_ptr()), grad.stride(0),
+                                         grad.stride(1), flags, gs))
     return loss, grad
 
 

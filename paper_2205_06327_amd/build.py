@@ -16,6 +16,7 @@ LIB = os.path.join(HERE, "libptycho.so")
 SOURCES = [
     os.path.join(HERE, "csrc", "ptycho_kernels.hip"),
     os.path.join(HERE, "csrc", "ptycho_api.cpp"),
+    os.path.join(HERE, "csrc", "ptycho_static.hip"),
 ]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,13 +14,16 @@
 #include <vector>
 
 #include "../../include/ptycho.h"
+#include "ptycho_host.h"
 #include "ptycho_kernels.h"
 
+namespace ptycho {
+namespace host {
+
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -35,11 +38,53 @@ int hip_fail(hipError_t e, const char* what) {
   return fail(PTYCHO_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define PT_HIP(call)                                   \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
+const char* last_error() { return g_err.c_str(); }
+
+// Host-side check of a caller buffer the kernels will address: it must be device memory of the
+// context's device, managed memory or pinned host memory, and, where the runtime knows the
+// allocation, [p, p + bytes) must lie inside it.  A pageable host pointer, another device's
+// memory or an overrun would otherwise reach the kernels as an invalid address.  Memory the
+// runtime reports without an address range (e.g. virtual-memory mappings) passes on its type.
+int check_buffer(int device, const void* p, size_t bytes, const char* what) {
+  if (!p || bytes == 0) return PTYCHO_OK;  // presence is checked by the callers
+  hipPointerAttribute_t at{};
+  hipError_t e = hipPointerGetAttributes(&at, p);
+  if (e != hipSuccess || at.type == hipMemoryTypeUnregistered) {
+    (void)hipGetLastError();
+    return fail(PTYCHO_E_ARG, "%s is not device-accessible memory (pageable host memory?)", what);
+  }
+  if (at.type == hipMemoryTypeDevice && at.device != device)
+    return fail(PTYCHO_E_ARG, "%s is on device %d, the context on device %d", what, at.device, device);
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess) {
+    const size_t off = static_cast<size_t>(static_cast<const char*>(p) - static_cast<const char*>(base));
+    if (off > size || bytes > size - off)
+      return fail(PTYCHO_E_SHAPE, "%s: %zu bytes from offset %zu overrun its %zu-byte allocation", what, bytes, off,
+                  size);
+  } else {
+    (void)hipGetLastError();
+  }
+  return PTYCHO_OK;
+}
+
+// Elements spanned by a [S][h][w] view with strides (slice_stride, ld), 0 when empty.  Saturates at
+// kSpanCap (beyond any allocation, small enough that byte counts do not wrap), so absurd strides
+// fail the allocation check instead of wrapping around to a small span.
+constexpr size_t kSpanCap = size_t(1) << 56;
+size_t span_elems(int64_t S, int64_t h, int64_t w, int64_t slice_stride, int64_t ld) {
+  if (S <= 0 || h <= 0 || w <= 0) return 0;
+  if (ld < 0 || (S > 1 && slice_stride < 0)) return kSpanCap;
+  const __int128 e = static_cast<__int128>(S - 1) * (S > 1 ? slice_stride : 0) + static_cast<__int128>(h - 1) * ld + w;
+  return e > static_cast<__int128>(kSpanCap) ? kSpanCap : static_cast<size_t>(e);
+}
+
+}  // namespace host
+}  // namespace ptycho
+
+using namespace ptycho::host;
+
+namespace {
 
 constexpr double kPi = 3.14159265358979323846264338327950288;
 
@@ -111,51 +156,6 @@ int check_object_args(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W
   return PTYCHO_OK;
 }
 
-// Host-side check of a caller buffer the kernels will address: it must be device memory of the
-// context's device, managed memory or pinned host memory, and, where the runtime knows the
-// allocation, [p, p + bytes) must lie inside it.  A pageable host pointer, another device's
-// memory or an overrun would otherwise reach the kernels as an invalid address.  Memory the
-// runtime reports without an address range (e.g. virtual-memory mappings) passes on its type.
-int check_buffer(int device, const void* p, size_t bytes, const char* what) {
-  if (!p || bytes == 0) return PTYCHO_OK;  // presence is checked by the callers
-  hipPointerAttribute_t at{};
-  hipError_t e = hipPointerGetAttributes(&at, p);
-  if (e != hipSuccess || at.type == hipMemoryTypeUnregistered) {
-    (void)hipGetLastError();
-    return fail(PTYCHO_E_ARG, "%s is not device-accessible memory (pageable host memory?)", what);
-  }
-  if (at.type == hipMemoryTypeDevice && at.device != device)
-    return fail(PTYCHO_E_ARG, "%s is on device %d, the context on device %d", what, at.device, device);
-  hipDeviceptr_t base = nullptr;
-  size_t size = 0;
-  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess) {
-    const size_t off = static_cast<size_t>(static_cast<const char*>(p) - static_cast<const char*>(base));
-    if (off > size || bytes > size - off)
-      return fail(PTYCHO_E_SHAPE, "%s: %zu bytes from offset %zu overrun its %zu-byte allocation", what, bytes, off,
-                  size);
-  } else {
-    (void)hipGetLastError();
-  }
-  return PTYCHO_OK;
-}
-
-// Elements spanned by a [S][h][w] view with strides (slice_stride, ld), 0 when empty.  Saturates at
-// kSpanCap (beyond any allocation, small enough that byte counts do not wrap), so absurd strides
-// fail the allocation check instead of wrapping around to a small span.
-constexpr size_t kSpanCap = size_t(1) << 56;
-size_t span_elems(int64_t S, int64_t h, int64_t w, int64_t slice_stride, int64_t ld) {
-  if (S <= 0 || h <= 0 || w <= 0) return 0;
-  if (ld < 0 || (S > 1 && slice_stride < 0)) return kSpanCap;
-  const __int128 e = static_cast<__int128>(S - 1) * (S > 1 ? slice_stride : 0) + static_cast<__int128>(h - 1) * ld + w;
-  return e > static_cast<__int128>(kSpanCap) ? kSpanCap : static_cast<size_t>(e);
-}
-
-#define PT_BUF(dev, p, bytes, what)                               \
-  do {                                                            \
-    int rc_ = check_buffer((dev), (p), (bytes), (what));          \
-    if (rc_ != PTYCHO_OK) return rc_;                             \
-  } while (0)
-
 // The object, probe, positions and (optional) patterns of a position call.
 int check_position_buffers(const ptycho_ctx* c, const void* obj, int32_t H, int32_t W, int64_t slice_stride,
                            int32_t ld, const void* probe, const int32_t* pos, int32_t n, const float* meas,
@@ -217,7 +217,7 @@ int run_loss_grad(ptycho_ctx* c, ptycho::KernelArgs a, int32_t gh, int32_t gw, d
 
 extern "C" {
 
-const char* ptycho_last_error(void) { return g_err.c_str(); }
+const char* ptycho_last_error(void) { return ptycho::host::last_error(); }
 const char* ptycho_version(void) { return "ptycho-mi355x 0.1 (gfx950)"; }
 
 int ptycho_create(ptycho_ctx** out, int32_t M, int32_t S, double wavelength_A, double dz_A, double pixel_A,

@@ -189,3 +189,18 @@ def test_gd_step_size_errors():
                                    ctypes.byref(out)) == -1
     assert out.value == -1.0  # nothing written on failure
     assert lib.ptycho_gd_step_size(None, 8, pos.ctypes.data_as(P), 2, 12, 12, 2, ctypes.byref(out)) == -1
+
+
+def test_static_entry_point_rejects_before_touching_the_device():
+    """ptycho_loss_grad_static: unsupported shapes and more positions than its static workspace holds are
+    rejected by host validation, before any HIP call."""
+    lib = pt.lib()
+    f = lib.ptycho_loss_grad_static
+    args = (0.0197, 2.0, 0.1, None, None, 256, 256, 256 * 256, 256, None, None)
+    assert f(96, 4, *args, 0, None, None, None, None, 0, 256, 0, None) == -6
+    assert "window size" in lib.ptycho_last_error().decode()
+    assert f(128, 0, *args, 0, None, None, None, None, 0, 256, 0, None) == -6
+    assert f(128, 4, *args, (1 << 20) + 1, None, None, None, None, 0, 256, 0, None) == -9
+    assert "static workspace" in lib.ptycho_last_error().decode()
+    assert f(128, 4, *args, -1, None, None, None, None, 0, 256, 0, None) == -1
+    assert f(128, 4, 0.0197, 2.0, 0.0, *args[3:], 0, None, None, None, None, 0, 256, 0, None) == -1
