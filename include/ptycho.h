@@ -218,7 +218,8 @@ int ptycho_loss_grad(ptycho_ctx* ctx, const void* obj, int32_t H, int32_t W, int
  * the checkpoint interval (see ptycho_set_checkpoint) and the number of
  * workgroups are chosen so that the store fits (M = 128, S = 16: interval 4).
  * Every call on a GPU uses the same array: calls that overlap on one GPU (two
- * streams, two host threads) race and must be serialised by the caller.
+ * streams, two host threads) race and must be serialised by the caller.  The
+ * call runs on the current device; a stream of another device is E_ARG.
  * Windows outside the object are skipped (loss 0) but cannot be reported
  * here: validate positions first (ptycho_validate_positions).
  * Errors as for ptycho_create / ptycho_loss_grad (the caller's buffers are

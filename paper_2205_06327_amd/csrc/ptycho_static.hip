@@ -134,6 +134,11 @@ extern "C" int ptycho_loss_grad_static(int32_t M, int32_t S, double wavelength_A
   if (rc != PTYCHO_OK) return rc;
   int dev = 0;
   PT_HIP(hipGetDevice(&dev));
+  if (stream != nullptr) {  // the array's address is the current device's: the stream must run there too
+    hipDevice_t sdev = 0;
+    PT_HIP(hipStreamGetDevice(static_cast<hipStream_t>(stream), &sdev));
+    if (sdev != dev) return fail(PTYCHO_E_ARG, "stream of device %d, current device %d", sdev, dev);
+  }
   const size_t M2 = static_cast<size_t>(M) * M;
   if (n > 0) {
     PT_BUF(dev, obj, span_elems(S, H, W, slice_stride, ld) * sizeof(float2), "object");
