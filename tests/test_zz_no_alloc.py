@@ -96,3 +96,42 @@ def test_static_entry_point_accumulates(torch_cuda):
     say(f"static, overwrite then accumulate: {name}")
     c, s = both(spec, problem(spec), accumulate_twice=True)
     check_pair(name + " (twice)", c, s, factor=2.0)
+
+
+def test_static_entry_point_edge_cases(torch_cuda):
+    """No positions: the gradient is zeroed and the loss is 0.  A window outside the object is skipped
+    on the device without a memory access (loss 0 for it), as by ptycho_loss_grad, whose context
+    reports it in its status word."""
+    import torch
+    import paper_2205_06327_amd as pt
+    name, spec = CALLS["m128"][1]
+    d = problem(spec)
+    t = to_dev(d)
+    say(f"static entry point, no positions: {name}")
+    grad = torch.full_like(t["obj"], complex(5.0, 5.0))
+    loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda:0")
+    empty_pos = torch.zeros((0, 2), dtype=torch.int32, device="cuda:0")
+    empty_meas = torch.zeros((0, spec.M, spec.M), dtype=torch.float32, device="cuda:0")
+    pt.ptycho_loss_grad_static(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A, t["obj"], t["probe"], empty_pos,
+                               empty_meas, grad=grad, loss=loss)
+    torch.cuda.synchronize()
+    assert float(loss.item()) == 0.0 and not bool(grad.abs().gt(0).any())
+    say(f"static entry point, one window outside the object: {name}")
+    pos = t["pos"].clone()
+    pos[1, 1] = spec.W - spec.M + 1  # one column past the right edge
+    n = pos.shape[0]
+    ctx = context(spec, n)
+    lpp_c = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+    loss_c, grad_c = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], pos, t["meas"], loss_per_pos=lpp_c)
+    with pytest.raises(pt.PtychoError) as e:
+        ctx.check()
+    assert e.value.name == "PTYCHO_E_BOUNDS"
+    lpp_s = torch.full((n,), -1.0, dtype=torch.float64, device="cuda:0")
+    loss_s, grad_s = pt.ptycho_loss_grad_static(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A, t["obj"],
+                                                t["probe"], pos, t["meas"], loss_per_pos=lpp_s)
+    torch.cuda.synchronize()
+    c = (float(loss_c.item()), lpp_c.cpu().numpy(), grad_c.cpu().numpy())
+    s = (float(loss_s.item()), lpp_s.cpu().numpy(), grad_s.cpu().numpy())
+    assert s[1][1] == 0.0 and c[1][1] == 0.0
+    check_pair(name + " (one window outside)", c, s)
+    ctx.close()
