@@ -1,5 +1,7 @@
 """Full-size parity on the GPU, on outputs the FP64 oracle can compute one by one.
 
+* 1 slice of 1024^2, 4096 positions (the whole single-slice scan): every
+  intensity, every per-position loss and the whole gradient against the oracle.
 * 8 slices of 1024^2, 4096 positions: the autograd.Function gradient (fused
   adjoint kernel) against central finite differences (h = 1e-3) of the FP64
   oracle loss on 64 random voxels, and against the oracle gradient there.
@@ -94,6 +96,38 @@ def test_autograd_gradient_vs_finite_differences_8_slices(torch_cuda):
     L_ref = sum(lookup[int(i)][0] for i in need if True)
     if len(need) == len(pos):
         assert abs(float(L.item()) - L_ref) <= 1e-5 * L_ref
+
+
+def test_single_slice_1024_full_scan_against_the_oracle(torch_cuda):
+    """Single-slice 1024^2 phase object, 128-windows, the whole 64 x 64 scan (4096 positions, step 14) with
+    Poisson counts at a dose of 1e5: all intensities (1e-5), all per-position losses and the total loss
+    (1e-5) and the whole gradient (1e-4) against the FP64 oracle."""
+    import torch
+    import paper_2205_06327_amd as pt
+    spec = ps.workload("2d-1024-m128")
+    say("1 x 1024^2, 4096 positions: oracle intensities, losses and gradient of the whole scan")
+    d = ps.build_inputs(spec)
+    H = oracle.fresnel_propagator(spec.M, spec.wavelength_A, spec.dz_A, spec.pixel_A)
+    I_true = oracle.forward(d["obj_true"], d["probe"], d["pos"], H)
+    meas = ps.poisson_counts(I_true, d["noise_seed"])
+    L_ref, lpp_ref, G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], meas, H)
+    dev = "cuda:0"
+    n = len(d["pos"])
+    ctx = pt.Context(spec.M, spec.S, spec.wavelength_A, spec.dz_A, spec.pixel_A, n)
+    probe = torch.tensor(d["probe"], dtype=torch.complex64, device=dev)
+    pos = torch.tensor(d["pos"], dtype=torch.int32, device=dev)
+    I = pt.ptycho_forward(ctx, torch.tensor(d["obj_true"], dtype=torch.complex64, device=dev), probe, pos)
+    lpp = torch.zeros(n, dtype=torch.float64, device=dev)
+    loss, grad = pt.ptycho_loss_grad(ctx, torch.tensor(d["obj_eval"], dtype=torch.complex64, device=dev), probe, pos,
+                                     torch.tensor(meas, dtype=torch.float32, device=dev), loss_per_pos=lpp)
+    assert ctx.check() == 0
+    torch.cuda.synchronize()
+    e_i = rel_l2(I.cpu().numpy(), I_true)
+    e_l = abs(float(loss.item()) - L_ref) / L_ref
+    e_g = rel_l2(grad.cpu().numpy(), G_ref)
+    say(f"  intensities {e_i:.2e}, loss {e_l:.2e}, gradient {e_g:.2e}")
+    assert e_i <= 1e-5 and e_l <= 1e-5 and e_g <= 1e-4
+    np.testing.assert_allclose(lpp.cpu().numpy(), lpp_ref, rtol=1e-5)
 
 
 @pytest.fixture(scope="module")
