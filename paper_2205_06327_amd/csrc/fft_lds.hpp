@@ -13,6 +13,10 @@
 //   layout C  thread (ky, jh)  registers (jl, m2) : DFT-16 along x (m2 -> j2),
 //                              j1 = jh*CJ + jl, CJ = X1/4
 //
+// In layout C, thread t = Y2*c + jh takes ky = 4*(c/16) + c%4 + Y1*((c/4)%4)
+// (layout_c_ky), so that a wave reads and writes only the exchange rows that
+// the same wave writes and reads in layout B (see the exchanges below).
+//
 // The inverse runs the same passes backwards with conjugate twiddles, so a
 // forward DFT, a pointwise multiply in layout C and an inverse DFT need no
 // reordering in between, and the inverse ends in layout A, where the next
@@ -284,11 +288,14 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 // E2 holds element (ky, j1, m2) in row Y2*(ky % Y1) + ky / Y1 at column
 // j1*X2 + (m2 ^ jh), jh = j1 / CJ.  The row order puts the E2 data of
 // layout-B thread (k1, m2) in the rows Y2*k1 .. Y2*k1 + 3 that hold its E1
-// data, so each wave of layout B reads and writes the same 16 whole rows in
-// both exchanges.  Banks: the row stride is odd (M + 3 complex), so the four
-// consecutive ky of a 16-lane layout-C access, Y2 rows apart, start 8 banks
-// apart (of 32), and the xor with jh spreads its four jh lanes within those
-// 8; every other access runs along a row.
+// data, so wave w of layout B (k1 = 4w .. 4w+3) reads and writes the same 16
+// whole rows 16w .. 16w+15 in both exchanges.  Those rows hold
+// ky = 4w + a + Y1*b (a, b = 0..3), which are exactly the ky of wave w in
+// layout C (layout_c_ky): the B <-> C exchange never crosses a wave.
+// Banks: the row stride is odd (M + 3 complex), so the four consecutive ky
+// of a 16-lane layout-C access (a = 0..3), Y2 rows apart, start 8 banks apart
+// (of 32), and the xor with jh spreads its four jh lanes within those 8;
+// every other access runs along a row.
 //
 // Barriers.  A thread that writes an exchange only overwrites slots that it,
 // or its own wave, read last:
@@ -298,11 +305,28 @@ __device__ __forceinline__ void pass_c(float2 (&c)[G::R]) {
 //     instruction stream, and LDS operations of one wave complete in order;
 //   * layout C writes exactly the slots it read (C -> B after B -> C);
 //   * layout A writes exactly the slots it read (A -> B after B -> A).
-// So the barrier before such a write is not needed; the barrier between the
-// writes and the reads of an exchange always is.  The first write of a
-// transform (layout A) keeps its barrier unless its caller knows that the
-// last access to the buffer was the layout-A read ending the previous
-// transform; otherwise the buffer may have served another purpose since.
+// So the barrier before such a write is not needed.  Between the writes and
+// the reads of an exchange, A <-> B needs a workgroup barrier; B <-> C stays
+// within each wave and needs only wave_sync, which keeps the compiler from
+// moving LDS accesses across it (the hardware already runs one wave's LDS
+// operations in order).  The first write of a transform (layout A) keeps its
+// barrier unless its caller knows that the last access to the buffer was the
+// layout-A read ending the previous transform; otherwise the buffer may have
+// served another purpose since.
+// ---------------------------------------------------------------------------
+template <class G>
+__device__ __forceinline__ int layout_c_ky(int tid) {
+  static_assert(G::Y2 == 4 && G::T % 64 == 0, "layout C pairing is written for Y2 = 4, whole waves");
+  const int c = tid / G::Y2;
+  return 4 * (c >> 4) + (c & 3) + G::Y1 * ((c >> 2) & 3);
+}
+// Orders the LDS accesses of one wave before and after this point (a
+// compiler fence at wavefront scope; no instruction is emitted).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 // ---------------------------------------------------------------------------
 template <class G>
 __device__ __forceinline__ void e1_write_a(float2* lds, const float2 (&v)[G::R], int n2, int x) {

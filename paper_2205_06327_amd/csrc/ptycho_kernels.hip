@@ -71,7 +71,7 @@ struct Lanes {
     x = tid % G::M;
     k1 = tid / G::X2;
     m2 = tid % G::X2;
-    ky = tid / G::Y2;
+    ky = layout_c_ky<G>(tid);
     jh = tid % G::Y2;
   }
 };
@@ -93,7 +93,7 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
   e1_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_fwd<G>(v, twb);
   e2_write_b<G>(lds, v, L.k1, L.m2);
-  __syncthreads();
+  wave_sync();
   e2_read_c<G>(lds, v, L.ky, L.jh);
   pass_c<G, false>(v);
   sfor<G::CJ>([&](auto lc) {
@@ -107,7 +107,7 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
   });
   pass_c<G, true>(v);
   e2_write_c<G>(lds, v, L.ky, L.jh);
-  __syncthreads();
+  wave_sync();
   e2_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_inv<G>(v, twb);
   e1_write_b<G>(lds, v, L.k1, L.m2);
@@ -128,7 +128,7 @@ __device__ __forceinline__ void dft2_a_to_c(float2 (&v)[G::R], float2* lds, cons
   e1_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_fwd<G>(v, twb);
   e2_write_b<G>(lds, v, L.k1, L.m2);
-  __syncthreads();
+  wave_sync();
   e2_read_c<G>(lds, v, L.ky, L.jh);
   pass_c<G, false>(v);
 }
@@ -141,7 +141,7 @@ __device__ __forceinline__ void idft2_c_to_a(float2 (&v)[G::R], float2* lds, con
   pass_c<G, true>(v);
   __syncthreads();
   e2_write_c<G>(lds, v, L.ky, L.jh);
-  __syncthreads();
+  wave_sync();
   e2_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_inv<G>(v, twb);
   e1_write_b<G>(lds, v, L.k1, L.m2);
