@@ -76,13 +76,18 @@ struct Lanes {
   }
 };
 
+struct NoHook {
+  __device__ __forceinline__ void operator()() const {}
+};
 // One full propagation IDFT(Hs * DFT(v)) in place, v in layout A at entry and
 // exit.  Hs = (hy * hx[kx]) for the forward propagator or its conjugate for
-// the adjoint, hy already carrying the 1/M^2 of the inverse transform.
-template <class G, bool ADJ>
+// the adjoint, hy already carrying the 1/M^2 of the inverse transform.  `late`
+// runs after the last exchange write, where the caller can issue loads for
+// its next step that then travel during the last barrier and pass.  
+template <class G, bool ADJ, class Hook = NoHook>
 __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const float2* hx_lds,
                                           const float2 (&twb)[G::X1], float2 hy, const Lanes<G>& L,
-                                          bool own_reads_last = false) {
+                                          bool own_reads_last = false, const Hook& late = Hook{}) {
   const int z = opaque_zero();
   lds += z;
   hx_lds += z;
@@ -111,6 +116,7 @@ __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const 
   e2_read_b<G>(lds, v, L.k1, L.m2);
   pass_b_inv<G>(v, twb);
   e1_write_b<G>(lds, v, L.k1, L.m2);
+  late();  // the wave's values sit in LDS here: the fewest registers are live
   __syncthreads();
   e1_read_a<G>(lds, v, L.n2, L.x);
   pass_a_inv<G>(v, L.n2);
@@ -321,7 +327,10 @@ __device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* _
 // The staging costs an LDS round trip and two barriers per slice, which pays
 // off for 128-windows over many slices (the tile walk) but not for 64-windows
 // or the short slice stacks of the batched launch.
-template <class G, int MODE, bool LINES = false, bool CKPT = false>
+// AHEAD: the adjoint sweep requests each stored incident wave one propagation
+// early (measured faster in the position-parallel launch, slower in the
+// batched one).
+template <class G, int MODE, bool LINES = false, bool CKPT = false, bool AHEAD = false>
 __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
                                                float2 hy, float2* __restrict__ ws, const Lanes<G>& L) {
   constexpr bool GRAD = MODE == kModeLossGrad || MODE == kModeLossGradProbe;
@@ -409,13 +418,18 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   idft2_c_to_a<G>(v, sh.lds, twb, L);  // chi_{S-1} = DFT^H g (its barriers make red[] visible)
   if (L.tid == 0)
     for (int w = 0; w < G::T / 64; ++w) f += sh.red[w];
-  // One adjoint step at slice s with psi_s from the store (w) or the probe (s = 0).
-  auto adjoint_step = [&](int s, const float2* __restrict__ w) {
-    // psi_s and the transmission window are loaded together and consumed
-    // before the gradient atomics are issued: memory operations retire in
-    // order, so loads issued behind the atomics would wait for them.  The
-    // atomics then drain while the next propagation runs on LDS and VALU.
-    float2 g[G::R];
+  // One adjoint step at slice s of the segment starting at seg, with psi_s
+  // from the store or the probe (s = 0).  psi_s and the transmission window
+  // are consumed before the gradient atomics are issued: a wave's memory
+  // operations retire in order, so its loads issued behind the atomics would
+  // wait for them.  The atomics then drain while the propagation runs on LDS
+  // and VALU; near its end (after its last exchange write) the loads of the
+  // next step's psi_{s-1}, when the store already holds it, are issued so that
+  // their latency overlaps the propagation's last barrier and pass.  (The
+  // window as well would not fit the registers there: it spills.)
+  float2 g[G::R];
+  bool pre = false;  // g holds psi_s, requested by the previous step
+  auto adjoint_step = [&](int s, int seg) {
     if (s == 0) {
       if constexpr (MODE == kModeLossGradProbe) {
         // dF/dP += chi_0 conj(t_0[window]) into this workgroup's partial sum (only this
@@ -435,7 +449,10 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = cmulc(v[decltype(rc)::value], g[decltype(rc)::value]); });
     } else {
-      sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
+      if (!pre) {
+        const float2* __restrict__ w = wave_slot(s, seg);
+        sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
+      }
       load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
       __builtin_amdgcn_sched_barrier(0);
       sfor<G::R>([&](auto rc) {
@@ -454,10 +471,29 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
     } else {
       scatter_add<G>(jb.grad + s * jb.gslice, jb.gld, g, L);
     }
-    if (s > 0) propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
+    if (s > 0) {
+      if constexpr (!AHEAD) {
+        propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L);
+      } else {
+        // psi_{s-1} is in the store now if it belongs to this segment or is a checkpoint (the inner
+        // waves of an earlier segment are recomputed first); slice 0 takes the probe at its own step
+        const int s1 = s - 1;
+        const bool nxt = s1 >= 1 && (s1 >= seg || s1 % ck == 0);
+        const float2* __restrict__ nw = nxt ? wave_slot(s1, s1 >= seg ? seg : s1) : ws;
+        propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L, false, [&]() {
+          // both branches define g, so it is not live across the propagation
+          if (nxt) {
+            sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&nw[decltype(rc)::value * G::T + L.tid]); });
+          } else {
+            sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = make_float2(0.f, 0.f); });
+          }
+        });
+        pre = nxt;
+      }
+    }
   };
   if constexpr (!CKPT) {
-    for (int s = S - 1; s >= 0; --s) adjoint_step(s, s > 0 ? wave_slot(s, s) : nullptr);
+    for (int s = S - 1; s >= 0; --s) adjoint_step(s, s);
   } else {
     for (int seg = last; seg >= 0; seg -= ck) {
       const int seg_end = seg + ck < S ? seg + ck : S;
@@ -482,8 +518,14 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
         }
         const float2* __restrict__ pk = park + opaque_zero();
         sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = load_nt(&pk[decltype(rc)::value * G::T + L.tid]); });
+        if constexpr (AHEAD) {
+          // the step below loads psi itself (nothing was requested across a segment boundary);
+          // defining g here keeps it from being live across the recomputation
+          sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = make_float2(0.f, 0.f); });
+          pre = false;
+        }
       }
-      for (int s = seg_end - 1; s >= seg; --s) adjoint_step(s, s > 0 ? wave_slot(s, seg) : nullptr);
+      for (int s = seg_end - 1; s >= seg; --s) adjoint_step(s, seg);
     }
   }
   __syncthreads();  // red[] and lds reuse by the next position
@@ -564,7 +606,7 @@ __global__ void __launch_bounds__(Geo<M>::T, kWavesPerSimd<M>) fused_kernel(Kern
     jb.probe = a.probe + static_cast<long long>(p) * a.probe_stride;
     jb.meas = a.meas + static_cast<long long>(p) * (G::M * G::M);
     jb.intens = a.intens + static_cast<long long>(p) * (G::M * G::M);
-    const double f = run_position<G, MODE, G::M == 128, true>(jb, sh, twb, hy, ws, L);
+    const double f = run_position<G, MODE, G::M == 128, true, true>(jb, sh, twb, hy, ws, L);
     if (LOSS && L.tid == 0) {
       a.loss_work[p] = f;
       if (a.loss_pos != nullptr) a.loss_pos[p] = f;
