@@ -83,7 +83,7 @@ struct NoHook {
 // exit.  Hs = (hy * hx[kx]) for the forward propagator or its conjugate for
 // the adjoint, hy already carrying the 1/M^2 of the inverse transform.  `late`
 // runs after the last exchange write, where the caller can issue loads for
-// its next step that then travel during the last barrier and pass.  
+// its next step that then travel during the last barrier and pass.
 template <class G, bool ADJ, class Hook = NoHook>
 __device__ __forceinline__ void propagate(float2 (&v)[G::R], float2* lds, const float2* hx_lds,
                                           const float2 (&twb)[G::X1], float2 hy, const Lanes<G>& L,
@@ -328,7 +328,7 @@ __device__ __forceinline__ float2 load_propagator(Shared<G>& sh, const float2* _
 // off for 128-windows over many slices (the tile walk) but not for 64-windows
 // or the short slice stacks of the batched launch.
 // AHEAD: the adjoint sweep requests each stored incident wave one propagation
-// early (measured faster in the position-parallel launch, slower in the
+// early (measured faster in the position-parallel launch, no faster in the
 // batched one).
 template <class G, int MODE, bool LINES = false, bool CKPT = false, bool AHEAD = false>
 __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>& sh, const float2 (&twb)[G::X1],
