@@ -30,16 +30,31 @@ __device__ __forceinline__ int opaque_zero() {
   return z;
 }
 
-// Streaming (non-temporal) access for the wave store: each stored wave is
-// read back once, so it should not displace the object windows and gradient
-// rows that neighbouring positions reuse from the caches.
-typedef float f2v __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void store_nt(float2* p, float2 e) {
-  __builtin_nontemporal_store(f2v{e.x, e.y}, reinterpret_cast<f2v*>(p));
+// A wave in a wave-store slot.  Streaming (non-temporal) accesses: each stored
+// wave is read back once, so it should not displace the object windows and
+// gradient rows that neighbouring positions reuse from the caches.  Register
+// pair (2q, 2q+1) of thread tid sits at complex offset 2*(q*T + tid), so each
+// access moves 16 bytes per lane, contiguous across the wave: half the memory
+// instructions of 8-byte accesses (measured 2.4 % faster over the whole
+// position-parallel launch).
+typedef float f4v __attribute__((ext_vector_type(4)));
+template <int R, int T>
+__device__ __forceinline__ void store_slot(float2* slot, const float2 (&v)[R], int tid) {
+  f4v* p = reinterpret_cast<f4v*>(slot) + tid;
+  sfor<R / 2>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    __builtin_nontemporal_store(f4v{v[2 * q].x, v[2 * q].y, v[2 * q + 1].x, v[2 * q + 1].y}, p + q * T);
+  });
 }
-__device__ __forceinline__ float2 load_nt(const float2* p) {
-  const f2v e = __builtin_nontemporal_load(reinterpret_cast<const f2v*>(p));
-  return make_float2(e.x, e.y);
+template <int R, int T>
+__device__ __forceinline__ void load_slot(float2 (&v)[R], const float2* slot, int tid) {
+  const f4v* p = reinterpret_cast<const f4v*>(slot) + tid;
+  sfor<R / 2>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const f4v e = __builtin_nontemporal_load(p + q * T);
+    v[2 * q] = make_float2(e.x, e.y);
+    v[2 * q + 1] = make_float2(e.z, e.w);
+  });
 }
 
 // Position index of the j-th job of this workgroup, or -1 when done.  Blocks
@@ -358,7 +373,7 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
   for (int s = 0; s < S; ++s) {
     if (GRAD && s >= 1 && (s % ck == 0 || s > last)) {
       float2* __restrict__ w = wave_slot(s, s % ck == 0 ? s : last);
-      sfor<G::R>([&](auto rc) { store_nt(&w[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
+      store_slot<G::R, G::T>(w, v, L.tid);
     }
     __builtin_amdgcn_sched_barrier(0);
     sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
@@ -451,7 +466,7 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
     } else {
       if (!pre) {
         const float2* __restrict__ w = wave_slot(s, seg);
-        sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
+        load_slot<G::R, G::T>(g, w, L.tid);
       }
       load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
       __builtin_amdgcn_sched_barrier(0);
@@ -483,7 +498,7 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
         propagate<G, true>(v, sh.lds, sh.hx, twb, hy, L, false, [&]() {
           // both branches define g, so it is not live across the propagation
           if (nxt) {
-            sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = load_nt(&nw[decltype(rc)::value * G::T + L.tid]); });
+            load_slot<G::R, G::T>(g, nw, L.tid);
           } else {
             sfor<G::R>([&](auto rc) { g[decltype(rc)::value] = make_float2(0.f, 0.f); });
           }
@@ -501,12 +516,12 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
         // recompute psi_{seg+1 .. seg_end-1} from the checkpoint; the adjoint wave waits in its slot
         float2* __restrict__ park = ws + static_cast<long long>(nck + (ck < S ? ck : S) - 1 + opaque_zero()) *
                                              (G::M * G::M);
-        sfor<G::R>([&](auto rc) { store_nt(&park[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
+        store_slot<G::R, G::T>(park, v, L.tid);
         if (seg == 0) {
           load_window<G>(v, jb.probe, G::M, L);
         } else {
           const float2* __restrict__ w = wave_slot(seg, seg);
-          sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = load_nt(&w[decltype(rc)::value * G::T + L.tid]); });
+          load_slot<G::R, G::T>(v, w, L.tid);
         }
         for (int s = seg; s + 1 < seg_end; ++s) {
           load_window<G>(t, jb.win + s * jb.sstride, jb.ld, L);
@@ -514,10 +529,10 @@ __device__ __forceinline__ double run_position(const PositionJob& jb, Shared<G>&
           sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = cmul(v[decltype(rc)::value], t[decltype(rc)::value]); });
           propagate<G, false>(v, sh.lds, sh.hx, twb, hy, L);
           float2* __restrict__ w = wave_slot(s + 1, seg);
-          sfor<G::R>([&](auto rc) { store_nt(&w[decltype(rc)::value * G::T + L.tid], v[decltype(rc)::value]); });
+          store_slot<G::R, G::T>(w, v, L.tid);
         }
         const float2* __restrict__ pk = park + opaque_zero();
-        sfor<G::R>([&](auto rc) { v[decltype(rc)::value] = load_nt(&pk[decltype(rc)::value * G::T + L.tid]); });
+        load_slot<G::R, G::T>(v, pk, L.tid);
         if constexpr (AHEAD) {
           // the step below loads psi itself (nothing was requested across a segment boundary);
           // defining g here keeps it from being live across the recomputation
