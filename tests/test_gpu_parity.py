@@ -308,6 +308,37 @@ def test_checkpointed_wave_recomputation(torch_cuda):
         ctx.set_checkpoint(0)
 
 
+@pytest.mark.parametrize("M", [64, 128])
+def test_short_stacks_checkpoint_intervals(torch_cuda, M):
+    """Stacks of 2, 3 and 5 slices with checkpoint intervals 1, 2 and 3, both window sizes: every
+    arrangement of checkpoints, inner waves, recomputed segments and stored waves requested one
+    propagation early in the adjoint sweep (stacks shorter than the interval included) gives the
+    oracle's gradient, and the losses do not depend on the interval."""
+    import torch
+    import paper_2205_06327_amd as pt
+    base = ps.workload("2d-256-m64" if M == 64 else "ms8-1024-m128")
+    for S in (2, 3, 5):
+        spec = ps.with_overrides(base, W=256 if M == 64 else 384, S=S, strength=0.05, ny=3, nx=3,
+                                 step=8 if M == 64 else 14)
+        say(f"M={M}, {S} slices, checkpoint intervals 1..3, 9 positions")
+        d = problem(spec)
+        t = to_dev(d)
+        ctx = context(spec, spec.n)
+        G_ref = oracle.loss_and_gradient(d["obj_eval"], d["probe"], d["pos"], d["meas"], d["H"])[2]
+        res = {}
+        for k in (1, 2, 3):
+            ctx.set_checkpoint(k)
+            lpp = torch.zeros(spec.n, dtype=torch.float64, device="cuda:0")
+            _, g = pt.ptycho_loss_grad(ctx, t["obj"], t["probe"], t["pos"], t["meas"], loss_per_pos=lpp)
+            assert ctx.check() == 0
+            torch.cuda.synchronize()
+            res[k] = (lpp.cpu().numpy(), g.cpu().numpy())
+        for k, (lk, gk) in res.items():
+            np.testing.assert_array_equal(lk, res[1][0])
+            assert rel_l2(gk, res[1][1]) <= 1e-6, (S, k)
+            assert rel_l2(gk, G_ref) <= TOL_G, (S, k)
+
+
 def test_potential_parametrisation_autograd(torch_cuda):
     """t = exp(i sigma V) and dF/dV = sigma Im(conj(t) dF/dt) in the library's kernels, through
     torch autograd, against the oracle's chain rule (pinned by central differences)."""
