@@ -191,21 +191,6 @@ __device__ __forceinline__ void load_window(float2 (&t)[G::R], const float2* __r
                                             const Lanes<G>& L) {
   for_window_rows<G>(base, ld, L, [&](auto rc, float2 e) { t[decltype(rc)::value] = e; });
 }
-// v *= window (conj_window: v *= conj(window)).  All loads are issued before
-// the first multiply (the scheduling fence keeps the compiler from
-// interleaving them), so the window costs one memory latency, not R.
-template <class G, bool CONJ>
-__device__ __forceinline__ void mul_window(float2 (&v)[G::R], const float2* __restrict__ base, long long ld,
-                                           const Lanes<G>& L) {
-  float2 t[G::R];
-  load_window<G>(t, base, ld, L);
-  __builtin_amdgcn_sched_barrier(0);
-  sfor<G::R>([&](auto rc) {
-    constexpr int r = decltype(rc)::value;
-    v[r] = CONJ ? cmulc(v[r], t[r]) : cmul(v[r], t[r]);
-  });
-}
-
 // Adds g (layout A) into the complex gradient rows.  permlane32_swap pairs
 // lanes l and l+32 so that each atomic instruction covers 32 consecutive
 // complex values (256 contiguous bytes) instead of every other float of 64.
